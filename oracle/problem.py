@@ -1,0 +1,61 @@
+"""One-stop set-up of the oracle for a mesh (test infrastructure).
+
+Bundles the steps of Sections 2-4 for a given mesh and order: numbering,
+geometry, lumped mass, node coordinates, operator, two-scale preconditioner
+and PCG.  Nothing here adds arithmetic of its own.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .coarse import CoarseCorrection
+from .geometry import Geometry, box_sizes, lumped_mass, node_coords_global
+from .gll import GLL
+from .numbering import number_mesh
+from .operator import apply_A, load_vector
+from .pcg import TwoScale, pcg
+from .schwarz import FinePreconditioner
+
+
+class Problem:
+    def __init__(self, vtx, hexes, n, fine=True, coarse=True, dirichlet=None):
+        self.vtx = np.asarray(vtx, dtype=np.float64)
+        self.hexes = np.asarray(hexes, dtype=np.int64)
+        self.n = n
+        self.gll = GLL(n)
+        self.num = number_mesh(self.hexes, n)
+        self.geo = Geometry(self.vtx, self.hexes, self.gll)
+        self.m = lumped_mass(self.num, self.geo)
+        self.x = node_coords_global(self.num, self.geo)
+        self.dirichlet = self.num.dirichlet if dirichlet is None else dirichlet
+        self._fine_on = fine
+        self._coarse_on = coarse
+        self._fine = None
+        self._coarse = None
+
+    @property
+    def fine(self):
+        if self._fine is None and self._fine_on:
+            self._fine = FinePreconditioner(self.num, self.hexes, self.vtx, self.gll,
+                                            box_sizes(self.vtx, self.hexes))
+        return self._fine
+
+    @property
+    def coarse(self):
+        if self._coarse is None and self._coarse_on:
+            self._coarse = CoarseCorrection(self.num, self.geo, self.gll, self.vtx, self.hexes,
+                                            self.m, self.dirichlet)
+        return self._coarse
+
+    def A(self, u):
+        return apply_A(self.num, self.geo, self.gll, u, self.dirichlet)
+
+    def precond(self, fine=True, coarse=True):
+        return TwoScale(self.fine if fine else None, self.coarse if coarse else None,
+                        self.dirichlet)
+
+    def load(self, s_fn):
+        return load_vector(self.num, self.m, s_fn(self.x), self.dirichlet)
+
+    def solve(self, b, rtol=1e-8, max_iter=2000, fine=True, coarse=True):
+        return pcg(self.A, b, self.precond(fine, coarse), rtol=rtol, max_iter=max_iter)
