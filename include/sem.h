@@ -1,0 +1,185 @@
+/*
+ * sem.h -- C ABI of the MI355X spectral-element Poisson solver.
+ *
+ * Method: Remacle, Gandham, Warburton, "GPU accelerated spectral finite
+ * elements on all-hex meshes".  The library solves the Poisson special case
+ * (kappa = 1, c = 0) of the model problem of Section 2 with homogeneous
+ * Dirichlet data, discretised with order-N Gauss-Lobatto-Legendre (GLL)
+ * spectral elements on unstructured hexahedra, by preconditioned conjugate
+ * gradients (Algorithm 1) with the two-scale additive Schwarz preconditioner
+ * of Section 4 (overlapping fast-diagonalisation patch solves plus an order-1
+ * coarse correction).
+ *
+ * Conventions shared by every entry point
+ *   - Mesh input is host memory and is copied; the handle owns every buffer it
+ *     allocates (host and device) until sem_mesh_destroy.
+ *   - Vectors passed to the hot-path calls (sem_apply_A, sem_precond,
+ *     sem_pcg_solve) are caller-owned DEVICE pointers of length n_global, in
+ *     the global node numbering described at sem_mesh_numbering.  Work is
+ *     enqueued on the caller's stream (a hipStream_t passed as void*, NULL =
+ *     the null stream).  sem_apply_A and sem_precond return once enqueued;
+ *     sem_pcg_solve synchronises its stream to return statistics.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ *   - Every function returns SEM_OK (0) or a negative status; no exception
+ *     crosses the ABI.  sem_last_error() gives a thread-local message.
+ *   - Supported orders: 2 <= N <= 15 (at N = 1 the extended 1D pencil of
+ *     Section 4.2 has no Dirichlet point and is singular).
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_mesh_s* sem_mesh;
+
+enum sem_status {
+  SEM_OK = 0,
+  SEM_EINVAL = -1,          /* bad argument (NULL pointer, size, vertex id out of range) */
+  SEM_ENOMEM = -2,          /* host or device allocation failed */
+  SEM_EMESH = -3,           /* invalid mesh: |J| <= 0 at a GLL node, face shared by > 2 hexes */
+  SEM_ENOCONV = -4,         /* max_iter / max_outer reached; statistics are filled */
+  SEM_EBREAKDOWN = -5,      /* p^T A p <= 0 or a non-finite scalar in PCG */
+  SEM_EHIP = -6,            /* a HIP / runtime library call failed */
+  SEM_EUNSUPPORTED = -7     /* order outside 2..15, or a call that needs a device on a host-only handle */
+};
+
+enum sem_dtype { SEM_F64 = 0, SEM_F32 = 1 };
+
+/* parts of the two-scale preconditioner P = P^c + P^f (Section 4) */
+enum sem_pc { SEM_PC_NONE = 0, SEM_PC_FINE = 1, SEM_PC_COARSE = 2, SEM_PC_TWOSCALE = 3 };
+
+enum sem_solve_mode { SEM_SOLVE_FP64 = 0, SEM_SOLVE_FP32_REFINED = 1 };
+
+typedef struct {
+  int device;        /* HIP device ordinal (default 0) */
+  int host_only;     /* 1: build the host tables only (numbering, geometry, patches) and
+                        allocate nothing on a device; hot-path calls return SEM_EUNSUPPORTED */
+  int build_fp32;    /* 1: also keep FP32 copies for SEM_F32 calls and the refined solve (default 1) */
+} sem_setup_opts;
+
+typedef struct {
+  int mode;          /* sem_solve_mode */
+  int pc;            /* sem_pc */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for FP64) */
+  int max_iter;      /* FP64: iteration cap; refined: cap on inner iterations per outer step */
+  int use_x0;        /* 1: start from the x passed in, else x = 0 */
+  double inner_rtol; /* refined form: relative tolerance of each FP32 inner solve */
+  int max_outer;     /* refined form: cap on outer (FP64 residual) steps */
+  int check_every;   /* read the convergence scalar back every k iterations (>= 1) */
+} sem_solve_opts;
+
+typedef struct {
+  int iterations;        /* total PCG iterations (inner iterations summed for the refined form) */
+  int outer_iterations;  /* refined form: number of FP64 residual corrections */
+  double rel_residual;   /* final ||r||_2 / ||b||_2 (true FP64 residual for the refined form) */
+  double solve_ms;       /* wall time of the solve on the host clock */
+  double* history;       /* optional caller buffer for ||r_k|| / ||b|| (may be NULL) */
+  int history_cap;
+  int history_len;
+} sem_solve_stats;
+
+/* Default option values. */
+void sem_default_setup_opts(sem_setup_opts* o);
+void sem_default_solve_opts(sem_solve_opts* o);
+
+/*
+ * sem_mesh_setup -- build every table of the discretisation for one mesh.
+ *   vtx   [n_vtx][3] vertex coordinates (host, row-major).
+ *   hex   [n_hex][8] vertex ids per hexahedron in tensor order: local corner
+ *         (a,b,c) in {0,1}^3 is entry a + 2b + 4c.  Any of the 24 proper
+ *         orientations is accepted.
+ *   order N of the GLL basis (Section 2.1), 2..15.
+ * Builds: the canonical global numbering and gather tables (Section 2.2),
+ * the geometric factors and lumped mass (Sections 2.3-2.4), the overlapping
+ * patch table and 1D fast-diagonalisation basis (Section 4.2), and the
+ * factorised order-1 coarse matrix (Section 4.1).  The default Dirichlet set
+ * is the topological boundary (nodes on faces owned by one hexahedron).
+ * Errors: SEM_EINVAL, SEM_EUNSUPPORTED (order), SEM_EMESH (|J| <= 0 at a GLL
+ * node, a face shared by more than two hexahedra), SEM_ENOMEM, SEM_EHIP.
+ */
+int sem_mesh_setup(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t n_hex,
+                   int order, const sem_setup_opts* opts, sem_mesh* out);
+
+int sem_mesh_destroy(sem_mesh m);
+
+/* n_global = number of global GLL nodes, n_local = n_hex (N+1)^3,
+   n_vertices = number of mesh vertices referenced by the hexahedra. */
+int sem_mesh_sizes(sem_mesh m, int64_t* n_global, int64_t* n_local, int64_t* n_vertices);
+
+/*
+ * sem_mesh_numbering -- the local-to-global table I_{l->g} of Section 2.2 (host out).
+ *   l2g [n_hex][(N+1)^3], local node (i,j,k) at i + (N+1) j + (N+1)^2 k.
+ * Canonical rule (the paper only asks for uniqueness): referenced vertices in
+ * ascending vertex id; then edges (sorted vertex pairs, lexicographic), N-1 ids
+ * each counted from the smaller vertex id; then faces (sorted 4-tuples,
+ * lexicographic), (N-1)^2 ids each in the frame whose origin is the face's
+ * smallest vertex id, p towards the smaller id of its two face-adjacent
+ * corners, id offset (q-1)(N-1) + (p-1); then element interiors, (N-1)^3
+ * per element, i fastest.
+ */
+int sem_mesh_numbering(sem_mesh m, int32_t* l2g_host);
+
+/* Gather table I_{g->l} of eq. (gather) as CSR (host out): offsets [n_global+1],
+   idx [n_local] = local indices, ascending within each global node. */
+int sem_mesh_gs_csr(sem_mesh m, int64_t* offsets_host, int32_t* idx_host);
+
+/* Overlapping patch table I^p of Section 4.2 (host out): [n_hex][(N+3)^3], patch
+   node (i,j,k), -1 <= i,j,k <= N+1, at (i+1) + (N+3)(j+1) + (N+3)^2 (k+1);
+   -1 marks a node outside the mesh (its residual is 0, its correction dropped). */
+int sem_mesh_patch_table(sem_mesh m, int32_t* ip_host);
+
+int sem_mesh_node_coords(sem_mesh m, double* xyz_host);   /* [n_global][3] */
+int sem_mesh_lumped_mass(sem_mesh m, double* mass_host);  /* [n_global], m_N of Section 4.1 */
+int sem_mesh_boundary_mask(sem_mesh m, uint8_t* mask_host); /* [n_global], 1 = Dirichlet */
+
+/* Geometric factors (host out): G [n_hex][6][(N+1)^3] = entries (xx,xy,xz,yy,yz,zz) of
+   rho_i rho_j rho_k |J| (J^T J)^{-1}, mass [n_hex][(N+1)^3] = rho_i rho_j rho_k |J|. */
+int sem_mesh_geometry(sem_mesh m, double* G_host, double* mass_host);
+
+/* Replace the Dirichlet set (host in, [n_global], 1 = Dirichlet).  Re-derives the
+   coarse vertex set and refactors the coarse matrix. */
+int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask_host);
+
+/*
+ * sem_apply_A -- y = mask(Q^T A_L Q u): the matrix-free stiffness action of
+ * eq. (R) / Algorithm 2 followed by the gather of eq. (gather) and the zeroing
+ * of Dirichlet nodes.  u, y: device vectors [n_global] of dtype (SEM_F64 /
+ * SEM_F32); the input is used as given (not masked).  u and y must not alias.
+ */
+int sem_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, void* stream);
+
+/*
+ * sem_precond -- z = mask(P^f r + P^c r), the two-scale preconditioner of
+ * Section 4: pc selects the parts (sem_pc).  P^f: patch gather through I^p,
+ * the fast-diagonalisation solve of eq. (z), additive scatter.  P^c: eq.
+ * (coarse) with the exact inverse of the coarse matrix, always in FP64.
+ * r, z: device vectors [n_global] of dtype; must not alias.
+ */
+int sem_precond(sem_mesh m, const void* r_dev, void* z_dev, int dtype, int pc, void* stream);
+
+/* Coarse solve only: Z = A_c^{-1} R on the free vertices (device FP64 vectors
+   [n_vertices] indexed by vertex global id; Dirichlet vertices give 0). */
+int sem_coarse_solve(sem_mesh m, const double* R_dev, double* Z_dev, void* stream);
+
+/*
+ * sem_pcg_solve -- Algorithm 1 for A x = b (b, x device FP64 [n_global]).
+ * SEM_SOLVE_FP64: every step in FP64.  SEM_SOLVE_FP32_REFINED: outer FP64
+ * iterative refinement (true residual b - A x in FP64) around inner PCG solves
+ * whose operator, gather and patch solves run in FP32, with FP64 dot products,
+ * scalars and coarse solve.  Returns SEM_OK, SEM_ENOCONV (stats filled),
+ * SEM_EBREAKDOWN, or an error.  b = 0 gives x = 0 and 0 iterations.
+ */
+int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solve_opts* o,
+                  sem_solve_stats* st, void* stream);
+
+const char* sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

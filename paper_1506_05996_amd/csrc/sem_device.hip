@@ -1,0 +1,806 @@
+// Device state, kernel launches and the C ABI of the spectral-element solver.
+#include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "sem_internal.h"
+#include "sem_kernels.h"
+
+namespace sem {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+#define SEM_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t err_ = (call);                                                             \
+    if (err_ != hipSuccess)                                                               \
+      throw ::sem::Error{SEM_EHIP, std::string(#call) + ": " + hipGetErrorString(err_)}; \
+  } while (0)
+
+// device buffer owned by a handle
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t err = hipMalloc((void**)&p, count * sizeof(T));
+    if (err != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{SEM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void upload(const T* h, size_t count) {
+    alloc(count);
+    if (count) SEM_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DBuf() { release(); }
+};
+
+template <typename TD, typename TS>
+static std::vector<TD> convert(const std::vector<TS>& v) {
+  return std::vector<TD>(v.begin(), v.end());
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+struct sem_mesh_s {
+  HostTables T;
+  bool host_only = false;
+  bool fp32 = true;
+  int device = 0;
+  // numbering / gather
+  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx;
+  DBuf<uint8_t> dir, fcount;
+  // operator
+  DBuf<double> G64, D64, w64;
+  DBuf<float> G32, D32, w32;
+  // fine preconditioner
+  DBuf<int32_t> ip, ip_off, ip_slot;
+  DBuf<double> S64, lam64, h64, zP64;
+  DBuf<float> S32, lam32, h32, zP32;
+  // coarse
+  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Zv, sinv, ac_val;
+  DBuf<int32_t> ac_off, ac_col;
+  // PCG work
+  DBuf<double> v64[5];
+  DBuf<float> v32[5];
+  DBuf<double> part, sc;
+};
+
+namespace {
+
+constexpr int kGS = 256;
+
+inline int64_t blocks_for(int64_t n, int t = kGS) { return std::max<int64_t>(1, (n + t - 1) / t); }
+inline int grid_stride_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), 8192); }
+
+template <typename T>
+const T* Gp(sem_mesh m);
+template <>
+const double* Gp<double>(sem_mesh m) { return m->G64.p; }
+template <>
+const float* Gp<float>(sem_mesh m) { return m->G32.p; }
+template <typename T>
+const T* Dp(sem_mesh m);
+template <>
+const double* Dp<double>(sem_mesh m) { return m->D64.p; }
+template <>
+const float* Dp<float>(sem_mesh m) { return m->D32.p; }
+template <typename T>
+T* Wp(sem_mesh m);
+template <>
+double* Wp<double>(sem_mesh m) { return m->w64.p; }
+template <>
+float* Wp<float>(sem_mesh m) { return m->w32.p; }
+template <typename T>
+T* ZPp(sem_mesh m);
+template <>
+double* ZPp<double>(sem_mesh m) { return m->zP64.p; }
+template <>
+float* ZPp<float>(sem_mesh m) { return m->zP32.p; }
+template <typename T>
+const T* Sp(sem_mesh m);
+template <>
+const double* Sp<double>(sem_mesh m) { return m->S64.p; }
+template <>
+const float* Sp<float>(sem_mesh m) { return m->S32.p; }
+template <typename T>
+const T* Lp(sem_mesh m);
+template <>
+const double* Lp<double>(sem_mesh m) { return m->lam64.p; }
+template <>
+const float* Lp<float>(sem_mesh m) { return m->lam32.p; }
+template <typename T>
+const T* Hp(sem_mesh m);
+template <>
+const double* Hp<double>(sem_mesh m) { return m->h64.p; }
+template <>
+const float* Hp<float>(sem_mesh m) { return m->h32.p; }
+
+// --- operator ---------------------------------------------------------------
+template <int N, typename T>
+void launch_ax(sem_mesh m, const T* u, T* y, hipStream_t s) {
+  constexpr int EPB = ax_epb<N>();
+  const HostTables& T_ = m->T;
+  const int64_t grid = (T_.E + EPB - 1) / EPB;
+  hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
+                     Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, T_.E);
+  SEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)blocks_for(T_.base_i)), dim3(kGS), 0, s, y, Wp<T>(m),
+                     m->vinc_off.p, m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1,
+                     T_.wedge_off, T_.wvert_off);
+  SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
+  switch (m->T.N) {
+#define CASE(NN) \
+  case NN:       \
+    launch_ax<NN, T>(m, u, y, s); \
+    break;
+    CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+    CASE(15)
+#undef CASE
+    default:
+      throw Error{SEM_EUNSUPPORTED, "order not compiled"};
+  }
+}
+
+// --- fine and coarse preconditioner -----------------------------------------
+template <int N, typename T>
+void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
+  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)m->T.E), dim3(fdm_threads<N>()), 0, s, r, ZPp<T>(m),
+                     m->ip.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->T.E);
+  SEM_HIP(hipGetLastError());
+}
+
+template <int N, typename T>
+void launch_restrict(sem_mesh m, const T* r, hipStream_t s) {
+  hipLaunchKernelGGL((restrict_kernel<N, T>), dim3((unsigned)m->T.E), dim3((N + 1) * (N + 1)), 0, s, r, m->Re.p,
+                     m->rec.p, m->phi.p, m->T.E);
+  SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void fdm_and_restrict(sem_mesh m, const T* r, bool fine, bool coarse, hipStream_t s) {
+  switch (m->T.N) {
+#define CASE(NN)                                        \
+  case NN:                                              \
+    if (fine) launch_fdm<NN, T>(m, r, s);               \
+    if (coarse) launch_restrict<NN, T>(m, r, s);        \
+    break;
+    CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+    CASE(15)
+#undef CASE
+    default:
+      throw Error{SEM_EUNSUPPORTED, "order not compiled"};
+  }
+}
+
+size_t max_level(const HostTables& T) {
+  size_t mx = 0;
+  for (auto& L : T.levels) mx = std::max<size_t>(mx, L.size);
+  return mx;
+}
+
+// Rlev (level order) -> Zv (vertex order): block LDL^T sweeps
+void coarse_solve_levels(sem_mesh m, hipStream_t s) {
+  const HostTables& T = m->T;
+  const int nl = (int)T.levels.size();
+  for (int k = 0; k < nl; ++k) {
+    const Level& L = T.levels[k];
+    const int grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, (L.size + 3) / 4));
+    hipLaunchKernelGGL(coarse_fwd_kernel, dim3(grid), dim3(256), L.size * sizeof(double), s, m->Rlev.p, m->Wlev.p,
+                       m->ac_off.p, m->ac_col.p, m->ac_val.p, m->sinv.p + L.sinv, L.off, L.size);
+    SEM_HIP(hipGetLastError());
+  }
+  for (int k = nl - 1; k >= 0; --k) {
+    const Level& L = T.levels[k];
+    const int grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, (L.size + 3) / 4));
+    hipLaunchKernelGGL(coarse_bwd_kernel, dim3(grid), dim3(256), L.size * sizeof(double), s, m->Xlev.p, m->Wlev.p,
+                       m->ac_off.p, m->ac_col.p, m->ac_val.p, m->sinv.p + L.sinv, L.off, L.size,
+                       (int)(k + 1 < nl));
+    SEM_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,
+                     m->cidx.p, T.V);
+  SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
+  const HostTables& H = m->T;
+  const bool fine = pc & SEM_PC_FINE, coarse = (pc & SEM_PC_COARSE) && H.nc > 0;
+  if (pc == SEM_PC_NONE) {
+    hipLaunchKernelGGL((copy_kernel<T, T>), dim3(grid_stride_blocks(H.n_global)), dim3(kGS), 0, s, z, r, H.n_global);
+    SEM_HIP(hipGetLastError());
+    return;
+  }
+  fdm_and_restrict<T>(m, r, fine, coarse, s);
+  if (coarse) {
+    hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, s, m->Rlev.p, m->Re.p,
+                       m->vinc_off.p, m->vinc_ec.p, m->cidx.p, H.V);
+    SEM_HIP(hipGetLastError());
+    coarse_solve_levels(m, s);
+  }
+  hipLaunchKernelGGL((precond_gather_kernel<T>), dim3((unsigned)blocks_for(H.n_global)), dim3(kGS), 0, s, z,
+                     (const T*)ZPp<T>(m), m->ip_off.p, m->ip_slot.p, m->dir.p, H.n_global, (int)fine,
+                     coarse ? (const double*)m->Zv.p : nullptr, m->owner.p, m->rec.p, m->phi.p, H.N);
+  SEM_HIP(hipGetLastError());
+}
+
+// --- coarse factorisation (set-up): Sinv_k = S_k^{-1}, S_k the Schur complements
+void factor_coarse(sem_mesh m) {
+  HostTables& T = m->T;
+  m->ac_off.upload(T.ac_off.data(), T.ac_off.size());
+  m->ac_col.upload(T.ac_col.data(), T.ac_col.size());
+  m->ac_val.upload(T.ac_val.data(), T.ac_val.size());
+  m->cidx.upload(T.cidx.data(), T.cidx.size());
+  const size_t nc = std::max<int64_t>(T.nc, 1);
+  m->Rlev.alloc(nc);
+  m->Wlev.alloc(nc);
+  m->Xlev.alloc(nc);
+  if (T.nc == 0) {
+    m->sinv.release();
+    return;
+  }
+  if (max_level(T) > 8192)
+    throw Error{SEM_EUNSUPPORTED, "coarse level of " + std::to_string(max_level(T)) + " vertices exceeds 8192"};
+  int64_t pool = 0;
+  for (auto& L : T.levels) pool += L.size * L.size;
+  m->sinv.alloc(pool);
+  rocblas_handle hb;
+  if (rocblas_create_handle(&hb) != rocblas_status_success) throw Error{SEM_EHIP, "rocblas_create_handle failed"};
+  std::unique_ptr<std::remove_pointer<rocblas_handle>::type, decltype(&rocblas_destroy_handle)> guard(
+      hb, rocblas_destroy_handle);
+  DBuf<double> Bd, Td;
+  DBuf<rocblas_int> info;
+  info.alloc(1);
+  const size_t mx = max_level(T);
+  Bd.alloc(mx * mx);
+  Td.alloc(mx * mx);
+  std::vector<double> dense;
+  for (size_t k = 0; k < T.levels.size(); ++k) {
+    const Level& L = T.levels[k];
+    // A_kk, column-major (symmetric)
+    dense.assign(L.size * L.size, 0.0);
+    for (int64_t r = 0; r < L.size; ++r)
+      for (int32_t q = T.ac_off[L.off + r]; q < T.ac_off[L.off + r + 1]; ++q) {
+        const int64_t c = T.ac_col[q] - L.off;
+        if (c >= 0 && c < L.size) dense[r + c * L.size] = T.ac_val[q];
+      }
+    double* Sk = m->sinv.p + L.sinv;
+    SEM_HIP(hipMemcpy(Sk, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (k > 0) {
+      const Level& P = T.levels[k - 1];
+      // B = A_{k-1,k}: rows of level k-1, columns of level k (column-major, ld = |P|)
+      dense.assign(P.size * L.size, 0.0);
+      for (int64_t r = 0; r < P.size; ++r)
+        for (int32_t q = T.ac_off[P.off + r]; q < T.ac_off[P.off + r + 1]; ++q) {
+          const int64_t c = T.ac_col[q] - L.off;
+          if (c >= 0 && c < L.size) dense[r + c * P.size] = T.ac_val[q];
+        }
+      SEM_HIP(hipMemcpy(Bd.p, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
+      const double one = 1.0, zero = 0.0, mone = -1.0;
+      const rocblas_int pn = (rocblas_int)P.size, ln = (rocblas_int)L.size;
+      // T = Sinv_{k-1} B
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, pn, ln, pn, &one,
+                        m->sinv.p + P.sinv, pn, Bd.p, pn, &zero, Td.p, pn) != rocblas_status_success)
+        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      // S_k = A_kk - B^T T
+      if (rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, ln, ln, pn, &mone, Bd.p, pn, Td.p,
+                        pn, &one, Sk, ln) != rocblas_status_success)
+        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+    }
+    if (rocsolver_dpotrf(hb, rocblas_fill_lower, (rocblas_int)L.size, Sk, (rocblas_int)L.size, info.p) !=
+        rocblas_status_success)
+      throw Error{SEM_EHIP, "rocsolver_dpotrf failed"};
+    rocblas_int ih = 0;
+    SEM_HIP(hipMemcpy(&ih, info.p, sizeof(ih), hipMemcpyDeviceToHost));
+    if (ih != 0) throw Error{SEM_EMESH, "coarse matrix is not positive definite"};
+    if (rocsolver_dpotri(hb, rocblas_fill_lower, (rocblas_int)L.size, Sk, (rocblas_int)L.size, info.p) !=
+        rocblas_status_success)
+      throw Error{SEM_EHIP, "rocsolver_dpotri failed"};
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)blocks_for(L.size * L.size)), dim3(kGS), 0, 0, Sk, L.size);
+    SEM_HIP(hipGetLastError());
+  }
+  SEM_HIP(hipDeviceSynchronize());
+}
+
+void upload_all(sem_mesh m) {
+  HostTables& T = m->T;
+  SEM_HIP(hipSetDevice(m->device));
+  m->rec.upload(T.rec.data(), T.rec.size());
+  m->vinc_off.upload(T.vinc_off.data(), T.vinc_off.size());
+  m->einc_off.upload(T.einc_off.data(), T.einc_off.size());
+  m->owner.upload(T.owner.data(), T.owner.size());
+  m->dir.upload(T.dir.data(), T.dir.size());
+  m->fcount.upload(T.fcount.data(), T.fcount.size());
+  {
+    // vertex incidence -> element * 8 + corner
+    std::vector<int32_t> ec(T.vinc_off.back());
+    std::vector<int32_t> fill(T.vinc_off.begin(), T.vinc_off.end() - 1);
+    const int N = T.N;
+    for (int64_t e = 0; e < T.E; ++e)
+      for (int p = 0; p < 8; ++p) {
+        const int64_t v = gid_of(T, e, (p & 1) * N, ((p >> 1) & 1) * N, (p >> 2) * N);
+        ec[fill[v]++] = (int32_t)(e * 8 + p);
+      }
+    m->vinc_ec.upload(ec.data(), ec.size());
+  }
+  m->G64.upload(T.G.data(), T.G.size());
+  m->D64.upload(T.D.data(), T.D.size());
+  m->w64.alloc(T.w_size);
+  m->ip.upload(T.ip.data(), T.ip.size());
+  m->ip_off.upload(T.ip_off.data(), T.ip_off.size());
+  m->ip_slot.upload(T.ip_slot.data(), T.ip_slot.size());
+  m->S64.upload(T.S.data(), T.S.size());
+  m->lam64.upload(T.lam.data(), T.lam.size());
+  m->h64.upload(T.h.data(), T.h.size());
+  m->zP64.alloc((size_t)T.E * T.np * T.np * T.np);
+  if (m->fp32) {
+    auto G32 = convert<float>(T.G);
+    m->G32.upload(G32.data(), G32.size());
+    auto D32 = convert<float>(T.D);
+    m->D32.upload(D32.data(), D32.size());
+    m->w32.alloc(T.w_size);
+    auto S32 = convert<float>(T.S);
+    m->S32.upload(S32.data(), S32.size());
+    auto l32 = convert<float>(T.lam);
+    m->lam32.upload(l32.data(), l32.size());
+    auto h32 = convert<float>(T.h);
+    m->h32.upload(h32.data(), h32.size());
+    m->zP32.alloc((size_t)T.E * T.np * T.np * T.np);
+  }
+  // Phi_I(t_i): row I = 0, 1
+  std::vector<double> phi(2 * T.n1);
+  for (int i = 0; i < T.n1; ++i) {
+    phi[i] = 0.5 * (1.0 - T.t[i]);
+    phi[T.n1 + i] = 0.5 * (1.0 + T.t[i]);
+  }
+  m->phi.upload(phi.data(), phi.size());
+  m->Re.alloc((size_t)T.E * 8);
+  m->Zv.alloc(std::max<int64_t>(T.V, 1));
+  m->part.alloc(kRedBlocks);
+  m->sc.alloc(16);
+  factor_coarse(m);
+}
+
+void ensure_work(sem_mesh m, bool need32) {
+  const int64_t n = m->T.n_global;
+  for (auto& b : m->v64)
+    if (b.n != (size_t)n) b.alloc(n);
+  if (need32)
+    for (auto& b : m->v32)
+      if (b.n != (size_t)n) b.alloc(n);
+}
+
+template <typename TA, typename TB>
+void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s) {
+  const int64_t n = m->T.n_global;
+  const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
+  hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, s, a, b, m->part.p, n);
+  SEM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dst, mode);
+  SEM_HIP(hipGetLastError());
+}
+
+double read_scalar(sem_mesh m, int idx, hipStream_t s) {
+  double v = 0.0;
+  SEM_HIP(hipMemcpyAsync(&v, m->sc.p + idx, sizeof(double), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+// One PCG solve (Algorithm 1) on vectors of type T; x, r in/out.  Returns
+// iterations; *rel gets ||r|| / rnorm0-scale; status via the return code.
+template <typename T>
+int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, int pc, int check_every,
+             hipStream_t s, int* iters, double* rel, sem_solve_stats* st) {
+  T* z;
+  T* p;
+  T* w;
+  if constexpr (std::is_same<T, double>::value) {
+    z = m->v64[2].p;
+    p = m->v64[3].p;
+    w = m->v64[4].p;
+  } else {
+    z = m->v32[2].p;
+    p = m->v32[3].p;
+    w = m->v32[4].p;
+  }
+  const int64_t n = m->T.n_global;
+  const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
+  const int gb = grid_stride_blocks(n);
+  hipLaunchKernelGGL((fill_kernel<double>), dim3(1), dim3(kGS), 0, s, m->sc.p, 0.0, (int64_t)7);
+  precond<T>(m, r, z, pc, s);
+  hipLaunchKernelGGL((copy_kernel<T, T>), dim3(gb), dim3(kGS), 0, s, p, z, n);
+  dot<T, T>(m, r, z, 0, 0, s);
+  const double tol2 = rtol * rtol * bnorm2;
+  int k = 0;
+  double rr = bnorm2;
+  int status = SEM_ENOCONV;
+  if (rr <= tol2) status = SEM_OK;
+  while (status != SEM_OK && k < max_iter) {
+    apply_A<T>(m, p, w, s);
+    dot<T, T>(m, p, w, 1, 1, s);
+    hipLaunchKernelGGL((update_xr_kernel<T, T>), dim3(nb), dim3(kRedThreads), 0, s, x, r, p, w, m->sc.p, m->part.p,
+                       n);
+    SEM_HIP(hipGetLastError());
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 4, 0);
+    ++k;
+    if (k % check_every == 0 || k == max_iter) {
+      rr = read_scalar(m, 4, s);
+      const double flag = read_scalar(m, 6, s);
+      if (st && st->history && st->history_len < st->history_cap)
+        st->history[st->history_len++] = std::sqrt(rr / bnorm2);
+      if (flag != 0.0 || !std::isfinite(rr)) {
+        status = SEM_EBREAKDOWN;
+        break;
+      }
+      if (rr <= tol2) {
+        status = SEM_OK;
+        break;
+      }
+    }
+    precond<T>(m, r, z, pc, s);
+    dot<T, T>(m, r, z, 5, 2, s);
+    hipLaunchKernelGGL((update_p_kernel<T>), dim3(gb), dim3(kGS), 0, s, p, z, m->sc.p, n);
+    SEM_HIP(hipGetLastError());
+  }
+  *iters = k;
+  *rel = std::sqrt(rr / bnorm2);
+  return status;
+}
+
+int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, sem_solve_stats* st,
+               hipStream_t s) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = m->T.n_global;
+  const bool refined = o->mode == SEM_SOLVE_FP32_REFINED;
+  if (refined && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+  ensure_work(m, refined);
+  const int gb = grid_stride_blocks(n);
+  const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
+  const int check = std::max(1, o->check_every);
+  if (st) st->history_len = 0;
+  dot<double, double>(m, b, b, 7, 0, s);
+  const double bnorm2 = read_scalar(m, 7, s);
+  int status = SEM_OK, iters = 0, outer = 0;
+  double rel = 0.0;
+  if (!std::isfinite(bnorm2)) {
+    status = SEM_EBREAKDOWN;
+  } else if (bnorm2 == 0.0) {
+    hipLaunchKernelGGL((fill_kernel<double>), dim3(gb), dim3(kGS), 0, s, x, 0.0, n);
+    SEM_HIP(hipGetLastError());
+    SEM_HIP(hipStreamSynchronize(s));
+  } else if (!refined) {
+    double* r = m->v64[1].p;
+    if (o->use_x0) {
+      apply_A<double>(m, x, m->v64[4].p, s);
+      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r, b, m->v64[4].p, m->part.p, n);
+    } else {
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(gb), dim3(kGS), 0, s, x, 0.0, n);
+      hipLaunchKernelGGL((copy_kernel<double, double>), dim3(gb), dim3(kGS), 0, s, r, b, n);
+    }
+    SEM_HIP(hipGetLastError());
+    status = pcg_core<double>(m, x, r, bnorm2, o->rtol, o->max_iter, o->pc, check, s, &iters, &rel, st);
+  } else {
+    // outer FP64 refinement around FP32 inner PCG solves
+    double* r64 = m->v64[1].p;
+    double* Ax = m->v64[4].p;
+    float* d32 = m->v32[0].p;
+    float* r32 = m->v32[1].p;
+    if (!o->use_x0) hipLaunchKernelGGL((fill_kernel<double>), dim3(gb), dim3(kGS), 0, s, x, 0.0, n);
+    status = SEM_ENOCONV;
+    const double tol2 = o->rtol * o->rtol * bnorm2;
+    for (outer = 0; outer <= o->max_outer; ++outer) {
+      apply_A<double>(m, x, Ax, s);
+      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r64, b, Ax, m->part.p, n);
+      hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 8, 0);
+      SEM_HIP(hipGetLastError());
+      const double rr = read_scalar(m, 8, s);
+      rel = std::sqrt(rr / bnorm2);
+      if (st && st->history && st->history_len < st->history_cap) st->history[st->history_len++] = rel;
+      if (!std::isfinite(rr)) {
+        status = SEM_EBREAKDOWN;
+        break;
+      }
+      if (rr <= tol2) {
+        status = SEM_OK;
+        break;
+      }
+      if (outer == o->max_outer) break;
+      const double rn = std::sqrt(rr);
+      hipLaunchKernelGGL(scale_to_f32_kernel, dim3(gb), dim3(kGS), 0, s, r32, r64, 1.0 / rn, n);
+      hipLaunchKernelGGL((fill_kernel<float>), dim3(gb), dim3(kGS), 0, s, d32, 0.0f, n);
+      SEM_HIP(hipGetLastError());
+      // ||r32||^2 of the scaled residual (about 1)
+      dot<float, float>(m, r32, r32, 9, 0, s);
+      const double r32n2 = read_scalar(m, 9, s);
+      int it = 0;
+      double irel = 0.0;
+      const int st_in = pcg_core<float>(m, d32, r32, r32n2, o->inner_rtol, o->max_iter, o->pc, check, s, &it, &irel,
+                                        nullptr);
+      iters += it;
+      if (st_in == SEM_EBREAKDOWN) {
+        status = SEM_EBREAKDOWN;
+        break;
+      }
+      hipLaunchKernelGGL(axpy_f32_kernel, dim3(gb), dim3(kGS), 0, s, x, d32, rn, n);
+      SEM_HIP(hipGetLastError());
+    }
+  }
+  SEM_HIP(hipStreamSynchronize(s));
+  if (st) {
+    st->iterations = iters;
+    st->outer_iterations = outer;
+    st->rel_residual = rel;
+    st->solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return SEM_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return SEM_EINVAL;
+  }
+}
+
+int need_device(sem_mesh m) {
+  if (!m) {
+    set_error("NULL handle");
+    return SEM_EINVAL;
+  }
+  if (m->host_only) {
+    set_error("host-only handle: no device state");
+    return SEM_EUNSUPPORTED;
+  }
+  return SEM_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void sem_default_setup_opts(sem_setup_opts* o) {
+  if (!o) return;
+  o->device = 0;
+  o->host_only = 0;
+  o->build_fp32 = 1;
+}
+
+void sem_default_solve_opts(sem_solve_opts* o) {
+  if (!o) return;
+  o->mode = SEM_SOLVE_FP64;
+  o->pc = SEM_PC_TWOSCALE;
+  o->rtol = 1e-8;
+  o->max_iter = 1000;
+  o->use_x0 = 0;
+  o->inner_rtol = 1e-3;
+  o->max_outer = 20;
+  o->check_every = 1;
+}
+
+const char* sem_last_error(void) { return g_last_error.c_str(); }
+
+int sem_mesh_setup(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t n_hex, int order,
+                   const sem_setup_opts* opts, sem_mesh* out) {
+  return guarded([&]() -> int {
+    if (!out || !vtx || !hex || n_vtx <= 0 || n_hex <= 0) throw Error{SEM_EINVAL, "NULL or empty mesh input"};
+    *out = nullptr;
+    if (order < 2 || order > 15) throw Error{SEM_EUNSUPPORTED, "order must be in 2..15"};
+    sem_setup_opts d;
+    sem_default_setup_opts(&d);
+    if (!opts) opts = &d;
+    auto m = std::make_unique<sem_mesh_s>();
+    m->host_only = opts->host_only != 0;
+    m->fp32 = opts->build_fp32 != 0;
+    m->device = opts->device;
+    HostTables& T = m->T;
+    build_reference(T, order);
+    build_numbering(T, hex, n_hex, n_vtx);
+    build_geometry(T, vtx, hex);
+    build_patches(T, hex);
+    build_coarse_matrices(T, vtx, hex);
+    build_coarse_levels(T);
+    if (!m->host_only) upload_all(m.get());
+    *out = m.release();
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_destroy(sem_mesh m) {
+  if (!m) return SEM_OK;
+  if (!m->host_only) (void)hipSetDevice(m->device);
+  delete m;
+  return SEM_OK;
+}
+
+int sem_mesh_sizes(sem_mesh m, int64_t* n_global, int64_t* n_local, int64_t* n_vertices) {
+  if (!m) return SEM_EINVAL;
+  if (n_global) *n_global = m->T.n_global;
+  if (n_local) *n_local = m->T.n_local;
+  if (n_vertices) *n_vertices = m->T.V;
+  return SEM_OK;
+}
+
+int sem_mesh_numbering(sem_mesh m, int32_t* l2g) {
+  if (!m || !l2g) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    export_l2g(m->T, l2g);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_gs_csr(sem_mesh m, int64_t* offsets, int32_t* idx) {
+  if (!m || !offsets || !idx) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    const HostTables& T = m->T;
+    std::vector<int32_t> l2g(T.n_local);
+    export_l2g(T, l2g.data());
+    std::fill(offsets, offsets + T.n_global + 1, 0);
+    for (int64_t x = 0; x < T.n_local; ++x) offsets[l2g[x] + 1]++;
+    for (int64_t g = 0; g < T.n_global; ++g) offsets[g + 1] += offsets[g];
+    std::vector<int64_t> fill(offsets, offsets + T.n_global);
+    for (int64_t x = 0; x < T.n_local; ++x) idx[fill[l2g[x]]++] = (int32_t)x;
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_patch_table(sem_mesh m, int32_t* ip) {
+  if (!m || !ip) return SEM_EINVAL;
+  std::copy(m->T.ip.begin(), m->T.ip.end(), ip);
+  return SEM_OK;
+}
+
+int sem_mesh_node_coords(sem_mesh m, double* xyz) {
+  if (!m || !xyz) return SEM_EINVAL;
+  std::copy(m->T.xN.begin(), m->T.xN.end(), xyz);
+  return SEM_OK;
+}
+
+int sem_mesh_lumped_mass(sem_mesh m, double* mass) {
+  if (!m || !mass) return SEM_EINVAL;
+  std::copy(m->T.mN.begin(), m->T.mN.end(), mass);
+  return SEM_OK;
+}
+
+int sem_mesh_boundary_mask(sem_mesh m, uint8_t* mask) {
+  if (!m || !mask) return SEM_EINVAL;
+  std::copy(m->T.dir.begin(), m->T.dir.end(), mask);
+  return SEM_OK;
+}
+
+int sem_mesh_geometry(sem_mesh m, double* G, double* mass) {
+  if (!m) return SEM_EINVAL;
+  if (G) std::copy(m->T.G.begin(), m->T.G.end(), G);
+  if (mass) std::copy(m->T.mass.begin(), m->T.mass.end(), mass);
+  return SEM_OK;
+}
+
+int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask) {
+  if (!m || !mask) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    HostTables& T = m->T;
+    for (int64_t g = 0; g < T.n_global; ++g) T.dir[g] = mask[g] ? 1 : 0;
+    // the coarse free set follows the vertex nodes: new levels, new factor
+    build_coarse_levels(T);
+    if (!m->host_only) {
+      SEM_HIP(hipSetDevice(m->device));
+      SEM_HIP(hipDeviceSynchronize());
+      m->dir.upload(T.dir.data(), T.dir.size());
+      factor_coarse(m);
+    }
+    return SEM_OK;
+  });
+}
+
+int sem_apply_A(sem_mesh m, const void* u, void* y, int dtype, void* stream) {
+  int st = need_device(m);
+  if (st) return st;
+  if (!u || !y || u == y) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SEM_F64)
+      apply_A<double>(m, (const double*)u, (double*)y, s);
+    else if (dtype == SEM_F32) {
+      if (!m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+      apply_A<float>(m, (const float*)u, (float*)y, s);
+    } else
+      throw Error{SEM_EINVAL, "dtype"};
+    return SEM_OK;
+  });
+}
+
+int sem_precond(sem_mesh m, const void* r, void* z, int dtype, int pc, void* stream) {
+  int st = need_device(m);
+  if (st) return st;
+  if (!r || !z || r == z || pc < 0 || pc > 3) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (dtype == SEM_F64)
+      precond<double>(m, (const double*)r, (double*)z, pc, s);
+    else if (dtype == SEM_F32) {
+      if (!m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+      precond<float>(m, (const float*)r, (float*)z, pc, s);
+    } else
+      throw Error{SEM_EINVAL, "dtype"};
+    return SEM_OK;
+  });
+}
+
+int sem_coarse_solve(sem_mesh m, const double* R, double* Z, void* stream) {
+  int st = need_device(m);
+  if (st) return st;
+  if (!R || !Z) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    hipStream_t s = (hipStream_t)stream;
+    const HostTables& T = m->T;
+    if (T.nc > 0) {
+      hipLaunchKernelGGL(coarse_gather_vertex_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Rlev.p, R,
+                         m->cidx.p, T.V);
+      SEM_HIP(hipGetLastError());
+      coarse_solve_levels(m, s);
+    } else {
+      hipLaunchKernelGGL((fill_kernel<double>), dim3(grid_stride_blocks(T.V)), dim3(kGS), 0, s, m->Zv.p, 0.0, T.V);
+    }
+    SEM_HIP(hipMemcpyAsync(Z, m->Zv.p, T.V * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return SEM_OK;
+  });
+}
+
+int sem_pcg_solve(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, sem_solve_stats* st,
+                  void* stream) {
+  int s0 = need_device(m);
+  if (s0) return s0;
+  if (!b || !x || b == x) return SEM_EINVAL;
+  sem_solve_opts d;
+  sem_default_solve_opts(&d);
+  if (!o) o = &d;
+  if (o->pc < 0 || o->pc > 3 || o->max_iter < 0 || !(o->rtol >= 0.0)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    return solve_impl(m, b, x, o, st, (hipStream_t)stream);
+  });
+}
+
+}  // extern "C"

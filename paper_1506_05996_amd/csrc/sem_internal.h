@@ -1,0 +1,98 @@
+// Internal state of a sem_mesh handle, shared by the host set-up (sem_setup.cpp)
+// and the device side (sem_device.hip).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+
+namespace sem {
+
+// Status carrier for internal code: never crosses the C ABI as an exception.
+struct Error {
+  int status;
+  std::string msg;
+};
+
+void set_error(const std::string& msg);
+
+// --- entity records ---------------------------------------------------------
+// Each element has 27 node classes: class c = cx + 3 cy + 9 cz with
+// cx = 0 (i = 0), 1 (0 < i < N), 2 (i = N), likewise cy, cz.  Class 13 is the
+// element interior, the 8 corner classes are vertices, 12 are edges and 6 faces.
+// For every class the global id of local node (i,j,k) is affine:
+//     gid = gbase + ai*i + aj*j + ak*k,
+// and so is its slot in the shared-node work array w (faces: 2 slots per face
+// node, edges and vertices: one slot per incident element):
+//     wid = wbase + ai*i + aj*j + ak*k.
+// Record layout (int32 x4): gbase, packed coefficients (three signed 10-bit
+// fields), wbase, flags.
+constexpr int kRecInts = 4;
+constexpr int kClasses = 27;
+constexpr int kInteriorClass = 13;
+constexpr int kFlagOwned = 1;     // this element holds the first local copy of the node
+constexpr int kFlagInterior = 2;  // interior node: written straight to the global vector
+
+inline int32_t pack_coef(int ai, int aj, int ak) {
+  return (ai & 0x3FF) | ((aj & 0x3FF) << 10) | ((ak & 0x3FF) << 20);
+}
+
+struct Level {
+  int64_t off;   // first coarse index of the level
+  int64_t size;  // number of free vertices in the level
+  int64_t sinv;  // offset of its dense inverse Schur complement in the Sinv pool
+};
+
+struct HostTables {
+  int N = 0, n1 = 0, np = 0;  // order, N+1, N+3
+  int64_t E = 0, n_global = 0, n_local = 0;
+  int64_t V = 0, n_edges = 0, n_faces = 0;
+  int64_t base_e = 0, base_f = 0, base_i = 0;  // first global id of edges, faces, interiors
+
+  // reference data
+  std::vector<double> t, rho, D;  // D[i*(N+1)+j] = phi_j'(t_i)
+  std::vector<double> S, lam;     // fast-diagonalisation basis [(N+3)^2], eigenvalues [N+3]
+
+  // numbering and gather
+  std::vector<int32_t> rec;              // [E][27][4]
+  std::vector<uint8_t> dir;              // [n_global] 1 = Dirichlet
+  std::vector<int32_t> vinc_off;         // [V+1]   vertex incidences (slot = index)
+  std::vector<int32_t> einc_off;         // [n_edges+1]
+  std::vector<uint8_t> fcount;           // [n_faces] 1 or 2 hexahedra
+  int64_t wedge_off = 0, wvert_off = 0, w_size = 0;
+  std::vector<int32_t> owner;            // [n_global] local index of the first copy
+
+  // faces and patches
+  std::vector<int32_t> face_nbr;         // [E][6][2] (element, local face) or -1
+  std::vector<int32_t> ip;               // [E][(N+3)^3] global id or -1
+  std::vector<int32_t> ip_off, ip_slot;  // inverse of ip (CSR over global ids, slots ascending)
+
+  // geometry
+  std::vector<double> G;     // [E][6][(N+1)^3]
+  std::vector<double> mass;  // [E][(N+1)^3]
+  std::vector<double> mN;    // [n_global]
+  std::vector<double> xN;    // [n_global][3]
+  std::vector<double> h;     // [E][3]
+
+  // coarse space (order-1 operator on the free vertices, level-ordered)
+  std::vector<int32_t> cidx;             // [V] coarse index or -1 (Dirichlet vertex)
+  int64_t nc = 0;                        // number of free vertices
+  std::vector<Level> levels;
+  std::vector<int32_t> ac_off, ac_col;   // CSR of A_c in level order
+  std::vector<double> ac_val;
+  std::vector<double> corner_K;          // [E][8][8] order-1 element matrices
+};
+
+// host set-up entry points (sem_setup.cpp)
+void build_reference(HostTables& T, int N);
+void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n_vtx);
+void build_geometry(HostTables& T, const double* vtx, const int64_t* hex);
+void build_patches(HostTables& T, const int64_t* hex);
+void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex);
+void build_coarse_levels(HostTables& T);
+void export_l2g(const HostTables& T, int32_t* l2g);
+int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k);
+
+}  // namespace sem

@@ -1,0 +1,547 @@
+// HIP kernels of the spectral-element solver for gfx950 (wave64, LDS-staged).
+// Included once, by sem_device.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+// elements per workgroup of the operator kernel: about 128 lanes per group
+template <int N>
+constexpr int ax_epb() {
+  return (128 / ((N + 1) * (N + 1))) > 0 ? (128 / ((N + 1) * (N + 1))) : 1;
+}
+
+__device__ __forceinline__ void unpack_coef(int32_t code, int& ai, int& aj, int& ak) {
+  ai = (int32_t)((uint32_t)code << 22) >> 22;
+  aj = (int32_t)((uint32_t)code << 12) >> 22;
+  ak = (int32_t)((uint32_t)code << 2) >> 22;
+}
+
+__device__ __forceinline__ int node_class(int x, int N) { return x == 0 ? 0 : (x == N ? 2 : 1); }
+
+// ---------------------------------------------------------------------------
+// Operator kernel, eq. (R) / Algorithm 2.  One (N+1)^2-lane group per element:
+// lane (i,j) keeps the k-pencil of u and of the result in registers, the
+// xi/eta contractions go through one LDS plane at a time.  Global ids come
+// from the element's entity records (scatter of eq. (scatter) fused into the
+// load); interior results go straight to y, shared-node results to the work
+// array w that the gather kernel sums.
+// ---------------------------------------------------------------------------
+template <int N, typename T, int EPB>
+__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
+ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
+          const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
+          int64_t E) {
+  constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
+  __shared__ T sD[P];
+  __shared__ T su[EPB][P];
+  __shared__ T sA[EPB][P];
+  __shared__ T sB[EPB][P];
+  const int tid = threadIdx.x;
+  const int le = tid / P, ij = tid - le * P;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t e = (int64_t)blockIdx.x * EPB + le;
+  const bool valid = e < E;
+  for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
+
+  const int cx = node_class(i, N), cy = node_class(j, N);
+  int gb[3], wb[3], fl[3], ai[3], aj[3], ak[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (valid) {
+      const int32_t* r = rec + ((e * kClasses + cx + 3 * cy + 9 * c) * kRecInts);
+      gb[c] = r[0];
+      unpack_coef(r[1], ai[c], aj[c], ak[c]);
+      wb[c] = r[2];
+      fl[c] = r[3];
+    } else {
+      gb[c] = wb[c] = fl[c] = ai[c] = aj[c] = ak[c] = 0;
+    }
+  }
+  T ru[n1], rw[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int c = node_class(k, N);
+    ru[k] = valid ? u[gb[c] + ai[c] * i + aj[c] * j + ak[c] * k] : T(0);
+    rw[k] = T(0);
+  }
+  const T* Ge = G + (valid ? e : 0) * 6 * NN + ij;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    su[le][ij] = ru[k];
+    __syncthreads();
+    T ur = 0, us = 0, ut = 0;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) {
+      ur += sD[i * n1 + m] * su[le][j * n1 + m];
+      us += sD[j * n1 + m] * su[le][m * n1 + i];
+      ut += sD[k * n1 + m] * ru[m];
+    }
+    const T g0 = Ge[0 * NN + k * P], g1 = Ge[1 * NN + k * P], g2 = Ge[2 * NN + k * P];
+    const T g3 = Ge[3 * NN + k * P], g4 = Ge[4 * NN + k * P], g5 = Ge[5 * NN + k * P];
+    const T A = g0 * ur + g1 * us + g2 * ut;
+    const T B = g1 * ur + g3 * us + g4 * ut;
+    const T C = g2 * ur + g4 * us + g5 * ut;
+    sA[le][ij] = A;
+    sB[le][ij] = B;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) rw[m] += sD[k * n1 + m] * C;
+    __syncthreads();
+    T acc = 0;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) acc += sD[m * n1 + i] * sA[le][j * n1 + m] + sD[m * n1 + j] * sB[le][m * n1 + i];
+    rw[k] += acc;
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int c = node_class(k, N);
+    const int off = ai[c] * i + aj[c] * j + ak[c] * k;
+    if (fl[c] & kFlagInterior) {
+      const int g = gb[c] + off;
+      y[g] = dir[g] ? T(0) : rw[k];
+    } else {
+      w[wb[c] + off] = rw[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gather of the shared nodes (eq. (gather)): one lane per shared global node,
+// copies summed in ascending element order, Dirichlet nodes zeroed.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict__ vinc_off,
+          const int32_t* __restrict__ einc_off, const uint8_t* __restrict__ fcount,
+          const uint8_t* __restrict__ dir, int64_t V, int64_t base_f, int64_t base_i, int m,
+          int64_t wedge_off, int64_t wvert_off) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= base_i) return;
+  T s = 0;
+  if (g < V) {
+    for (int32_t q = vinc_off[g]; q < vinc_off[g + 1]; ++q) s += w[wvert_off + q];
+  } else if (g < base_f) {
+    const int64_t q = g - V, ed = q / m, r = q - ed * m;
+    for (int32_t x = einc_off[ed]; x < einc_off[ed + 1]; ++x) s += w[wedge_off + (int64_t)x * m + r];
+  } else {
+    const int64_t mm = (int64_t)m * m, q = g - base_f, f = q / mm, r = q - f * mm;
+    s = w[2 * f * mm + r];
+    if (fcount[f] == 2) s += w[(2 * f + 1) * mm + r];
+  }
+  y[g] = dir[g] ? T(0) : s;
+}
+
+// ---------------------------------------------------------------------------
+// Fine patch solve, eq. (z), one workgroup per subdomain.  The (N+3)^3 patch
+// is gathered through I^p into LDS; each of the six 1D contractions is done
+// by lanes that own a whole pencil in registers (one LDS read and one write
+// per node and pass); the diagonal scaling is fused into the zeta pass.
+// ---------------------------------------------------------------------------
+template <int N>
+constexpr int fdm_threads() {
+  return (((N + 3) * (N + 3) + 63) / 64) * 64;
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(fdm_threads<N>())
+fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restrict__ ip,
+           const T* __restrict__ Sg, const T* __restrict__ lamg, const T* __restrict__ hg, int64_t E) {
+  constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
+  __shared__ T X[MMM];
+  __shared__ T S[MM];
+  __shared__ T lam[m];
+  const int tid = threadIdx.x;
+  const int64_t e = blockIdx.x;
+  for (int x = tid; x < MM; x += NT) S[x] = Sg[x];
+  if (tid < m) lam[tid] = lamg[tid];
+  const int32_t* ipe = ip + e * MMM;
+  for (int x = tid; x < MMM; x += NT) {
+    const int32_t g = ipe[x];
+    X[x] = g >= 0 ? r[g] : T(0);
+  }
+  __syncthreads();
+  const T hx = hg[e * 3 + 0], hy = hg[e * 3 + 1], hz = hg[e * 3 + 2];
+  const T ihx2 = T(4) / (hx * hx), ihy2 = T(4) / (hy * hy), ihz2 = T(4) / (hz * hz);
+  const T vscale = T(8) / (hx * hy * hz);
+  const bool act = tid < MM;
+  const int p0 = tid % m, p1 = tid / m;
+  T v[m], o[m];
+  // pass 1: xi, S^T   (lane owns row (b = p0, c = p1))
+  if (act) {
+    T* row = X + p1 * MM + p0 * m;
+#pragma unroll
+    for (int a = 0; a < m; ++a) v[a] = row[a];
+#pragma unroll
+    for (int a2 = 0; a2 < m; ++a2) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < m; ++a) s += S[a * m + a2] * v[a];
+      row[a2] = s;
+    }
+  }
+  __syncthreads();
+  // pass 2: eta, S^T  (lane owns column (a = p0, c = p1))
+  if (act) {
+    T* col = X + p1 * MM + p0;
+#pragma unroll
+    for (int b = 0; b < m; ++b) v[b] = col[b * m];
+#pragma unroll
+    for (int b2 = 0; b2 < m; ++b2) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < m; ++b) s += S[b * m + b2] * v[b];
+      col[b2 * m] = s;
+    }
+  }
+  __syncthreads();
+  // pass 3: zeta, S^T, diagonal, S  (lane owns pencil (a = p0, b = p1))
+  if (act) {
+    T* pen = X + p1 * m + p0;
+#pragma unroll
+    for (int c = 0; c < m; ++c) v[c] = pen[c * MM];
+    const T dab = lam[p0] * ihx2 + lam[p1] * ihy2;
+#pragma unroll
+    for (int c2 = 0; c2 < m; ++c2) {
+      T s = 0;
+#pragma unroll
+      for (int c = 0; c < m; ++c) s += S[c * m + c2] * v[c];
+      o[c2] = s / (dab + lam[c2] * ihz2);
+    }
+#pragma unroll
+    for (int c = 0; c < m; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int c2 = 0; c2 < m; ++c2) s += S[c * m + c2] * o[c2];
+      pen[c * MM] = s;
+    }
+  }
+  __syncthreads();
+  // pass 4: eta, S
+  if (act) {
+    T* col = X + p1 * MM + p0;
+#pragma unroll
+    for (int b = 0; b < m; ++b) v[b] = col[b * m];
+#pragma unroll
+    for (int b = 0; b < m; ++b) {
+      T s = 0;
+#pragma unroll
+      for (int b2 = 0; b2 < m; ++b2) s += S[b * m + b2] * v[b2];
+      col[b * m] = s;
+    }
+  }
+  __syncthreads();
+  // pass 5: xi, S, and the volume factor 8/(hx hy hz)
+  if (act) {
+    T* row = X + p1 * MM + p0 * m;
+#pragma unroll
+    for (int a = 0; a < m; ++a) v[a] = row[a];
+#pragma unroll
+    for (int a = 0; a < m; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int a2 = 0; a2 < m; ++a2) s += S[a * m + a2] * v[a2];
+      row[a] = s * vscale;
+    }
+  }
+  __syncthreads();
+  T* zPe = zP + e * MMM;
+  for (int x = tid; x < MMM; x += NT) zPe[x] = X[x];
+}
+
+// ---------------------------------------------------------------------------
+// Additive accumulation P^f[I^p] += z_s (slots of each global node summed in
+// ascending order), plus the coarse prolongation (I Z)_N evaluated at the
+// node's first local copy, then the Dirichlet mask.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+precond_gather_kernel(T* __restrict__ z, const T* __restrict__ zP, const int32_t* __restrict__ ip_off,
+                      const int32_t* __restrict__ ip_slot, const uint8_t* __restrict__ dir, int64_t ng,
+                      int use_fine, const double* __restrict__ Zv, const int32_t* __restrict__ owner,
+                      const int32_t* __restrict__ rec, const double* __restrict__ phi, int N) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= ng) return;
+  T s = 0;
+  if (use_fine)
+    for (int32_t q = ip_off[g]; q < ip_off[g + 1]; ++q) s += zP[ip_slot[q]];
+  if (Zv != nullptr) {
+    const int n1 = N + 1, nn = n1 * n1 * n1;
+    const int32_t o = owner[g];
+    const int64_t e = o / nn;
+    const int loc = o - (int)e * nn;
+    const int i = loc % n1, j = (loc / n1) % n1, k = loc / (n1 * n1);
+    double acc = 0.0;
+    for (int c = 0; c < 8; ++c) {
+      const int I = c & 1, J = (c >> 1) & 1, K = c >> 2;
+      const int cls = 2 * I + 3 * (2 * J) + 9 * (2 * K);
+      const int32_t v = rec[(e * kClasses + cls) * kRecInts];
+      acc += phi[I * n1 + i] * phi[J * n1 + j] * phi[K * n1 + k] * Zv[v];
+    }
+    s += (T)acc;
+  }
+  z[g] = dir[g] ? T(0) : s;
+}
+
+// Coarse restriction, per element: R_e[IJK] = sum over the nodes this element
+// owns of Phi_I(t_i) Phi_J(t_j) Phi_K(t_k) r_N  (= (I^T r) once gathered).
+template <int N, typename T>
+__global__ void __launch_bounds__((N + 1) * (N + 1))
+restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t* __restrict__ rec,
+                const double* __restrict__ phi, int64_t E) {
+  constexpr int n1 = N + 1, P = n1 * n1;
+  __shared__ double red[8][P];
+  const int tid = threadIdx.x;
+  const int i = tid % n1, j = tid / n1;
+  const int64_t e = blockIdx.x;
+  const int cx = node_class(i, N), cy = node_class(j, N);
+  double acc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int cz = node_class(k, N);
+    const int32_t* rr = rec + ((e * kClasses + cx + 3 * cy + 9 * cz) * kRecInts);
+    if (rr[3] & kFlagOwned) {
+      int ai, aj, ak;
+      unpack_coef(rr[1], ai, aj, ak);
+      const double v = (double)r[rr[0] + ai * i + aj * j + ak * k];
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        acc[c] += phi[(c & 1) * n1 + i] * phi[((c >> 1) & 1) * n1 + j] * phi[(c >> 2) * n1 + k] * v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) red[c][tid] = acc[c];
+  __syncthreads();
+  if (tid < 8) {
+    double s = 0.0;
+    for (int x = 0; x < P; ++x) s += red[tid][x];
+    Re[e * 8 + tid] = s;
+  }
+}
+
+// coarse residual on the free vertices (level order): sum of the element parts
+__global__ void __launch_bounds__(256)
+restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, const int32_t* __restrict__ vinc_off,
+                       const int32_t* __restrict__ vinc_ec, const int32_t* __restrict__ cidx, int64_t V) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int32_t c = cidx[v];
+  if (c < 0) return;
+  double s = 0.0;
+  for (int32_t q = vinc_off[v]; q < vinc_off[v + 1]; ++q) s += Re[vinc_ec[q]];
+  R[c] = s;
+}
+
+// Block LDL^T solve of the level-ordered coarse matrix.  Forward sweep for
+// level k: yhat = R_k - A_{k,k-1} W_{k-1} (recomputed by every workgroup in
+// LDS), then W_k = Sinv_k yhat, one wave per row.
+__global__ void __launch_bounds__(256)
+coarse_fwd_kernel(const double* __restrict__ R, double* __restrict__ W, const int32_t* __restrict__ off,
+                  const int32_t* __restrict__ col, const double* __restrict__ val, const double* __restrict__ Sinv,
+                  int64_t loff, int64_t lsize) {
+  extern __shared__ double yh[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int64_t r = tid; r < lsize; r += nt) {
+    double s = R[loff + r];
+    for (int32_t q = off[loff + r]; q < off[loff + r + 1]; ++q)
+      if (col[q] < loff) s -= val[q] * W[col[q]];
+    yh[r] = s;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  for (int64_t row = (int64_t)blockIdx.x * nw + wave; row < lsize; row += (int64_t)gridDim.x * nw) {
+    const double* Sr = Sinv + row * lsize;
+    double s = 0.0;
+    for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * yh[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) W[loff + row] = s;
+  }
+}
+
+// Backward sweep for level k: X_k = W_k - Sinv_k (A_{k,k+1} X_{k+1}).
+__global__ void __launch_bounds__(256)
+coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ W, const int32_t* __restrict__ off,
+                  const int32_t* __restrict__ col, const double* __restrict__ val, const double* __restrict__ Sinv,
+                  int64_t loff, int64_t lsize, int has_next) {
+  extern __shared__ double tt[];
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int64_t nxt = loff + lsize;
+  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+  if (!has_next) {
+    for (int64_t r = (int64_t)blockIdx.x * nt + tid; r < lsize; r += (int64_t)gridDim.x * nt) X[loff + r] = W[loff + r];
+    return;
+  }
+  for (int64_t r = tid; r < lsize; r += nt) {
+    double s = 0.0;
+    for (int32_t q = off[loff + r]; q < off[loff + r + 1]; ++q)
+      if (col[q] >= nxt) s += val[q] * X[col[q]];
+    tt[r] = s;
+  }
+  __syncthreads();
+  for (int64_t row = (int64_t)blockIdx.x * nw + wave; row < lsize; row += (int64_t)gridDim.x * nw) {
+    const double* Sr = Sinv + row * lsize;
+    double s = 0.0;
+    for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * tt[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) X[loff + row] = W[loff + row] - s;
+  }
+}
+
+// vertex-indexed coarse solution (0 on Dirichlet vertices)
+__global__ void __launch_bounds__(256)
+coarse_scatter_kernel(double* __restrict__ Zv, const double* __restrict__ X, const int32_t* __restrict__ cidx,
+                      int64_t V) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int32_t c = cidx[v];
+  Zv[v] = c >= 0 ? X[c] : 0.0;
+}
+
+__global__ void __launch_bounds__(256)
+coarse_gather_vertex_kernel(double* __restrict__ Rlev, const double* __restrict__ Rv, const int32_t* __restrict__ cidx,
+                            int64_t V) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int32_t c = cidx[v];
+  if (c >= 0) Rlev[c] = Rv[v];
+}
+
+// copy the lower triangle of a column-major n x n matrix to the upper one
+__global__ void symmetrize_kernel(double* __restrict__ A, int64_t n) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n * n) return;
+  const int64_t r = x % n, c = x / n;
+  if (r < c) A[r + c * n] = A[c + r * n];
+}
+
+// ---------------------------------------------------------------------------
+// PCG vector kernels (Algorithm 1).  Reductions are two-pass with a fixed
+// grid and a fixed tree order, so results are reproducible run to run.
+// Scalars live on the device: sc[0] = z^T r, sc[1] = p^T w, sc[2] = alpha,
+// sc[3] = beta, sc[4] = r^T r, sc[5] = scratch, sc[6] = breakdown flag.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 1024;
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += sh[q];
+  return s;
+}
+
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(kRedThreads)
+dot_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, double* __restrict__ part, int64_t n) {
+  __shared__ double sh[kRedThreads / 64];
+  double s = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+    s += (double)a[x] * (double)b[x];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// mode 0: sc[dst] = sum;  mode 1: alpha = sc[0] / sum (p^T w);  mode 2: beta = sum / sc[0], sc[0] = sum
+__global__ void __launch_bounds__(kRedThreads)
+dot_final_kernel(const double* __restrict__ part, double* __restrict__ sc, int nparts, int dst, int mode) {
+  __shared__ double sh[kRedThreads / 64];
+  double s = 0.0;
+  for (int x = threadIdx.x; x < nparts; x += blockDim.x) s += part[x];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) {
+    sc[dst] = s;
+    if (mode == 1) {
+      const double a = sc[0] / s;
+      if (!(s > 0.0) || !isfinite(a)) sc[6] = 1.0;
+      sc[2] = a;
+    } else if (mode == 2) {
+      const double bta = s / sc[0];
+      if (!isfinite(bta)) sc[6] = 1.0;
+      sc[3] = bta;
+      sc[0] = s;
+    }
+  }
+}
+
+// x += alpha p; r -= alpha w; partial sums of r^T r
+template <typename T, typename TX>
+__global__ void __launch_bounds__(kRedThreads)
+update_xr_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ w,
+                 const double* __restrict__ sc, double* __restrict__ part, int64_t n) {
+  __shared__ double sh[kRedThreads / 64];
+  const double alpha = sc[2];
+  const T al = (T)alpha;
+  double s = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    x[q] += (TX)(al * p[q]);
+    const T rn = r[q] - al * w[q];
+    r[q] = rn;
+    s += (double)rn * (double)rn;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// p = z + beta p
+template <typename T>
+__global__ void __launch_bounds__(256)
+update_p_kernel(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ sc, int64_t n) {
+  const T beta = (T)sc[3];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    p[q] = z[q] + beta * p[q];
+}
+
+template <typename TD, typename TS>
+__global__ void __launch_bounds__(256) copy_kernel(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    d[q] = (TD)s[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) fill_kernel(T* __restrict__ d, T v, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    d[q] = v;
+}
+
+// r = b - Ax (FP64) with partial sums of r^T r
+__global__ void __launch_bounds__(kRedThreads)
+residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ Ax,
+                double* __restrict__ part, int64_t n) {
+  __shared__ double sh[kRedThreads / 64];
+  double s = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const double v = b[q] - Ax[q];
+    r[q] = v;
+    s += v * v;
+  }
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// f32 = (float)(r64 * scale)
+__global__ void __launch_bounds__(256)
+scale_to_f32_kernel(float* __restrict__ d, const double* __restrict__ s, double scale, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    d[q] = (float)(s[q] * scale);
+}
+
+// x64 += scale * d32
+__global__ void __launch_bounds__(256)
+axpy_f32_kernel(double* __restrict__ x, const float* __restrict__ d, double scale, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    x[q] += scale * (double)d[q];
+}
+
+}  // namespace sem

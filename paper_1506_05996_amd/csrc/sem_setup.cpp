@@ -1,0 +1,926 @@
+// Host-side set-up of the spectral-element discretisation (runs once per mesh).
+//
+//  * 1D reference data: GLL points and weights, derivative matrix (Section 2.1),
+//    extended 1D pencil and its generalised eigenbasis (Section 4.2).
+//  * Canonical global numbering as per-element affine "entity records" and
+//    the gather structure of eq. (gather) (Section 2.2).
+//  * Geometric factors, weighted mass, lumped mass (Sections 2.3-2.4).
+//  * Overlapping patch table I^p and its inverse (Section 4.2).
+//  * Order-1 coarse matrix on the free vertices with a BFS level ordering that
+//    makes it block tridiagonal (Section 4.1).
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <numeric>
+#include <thread>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+namespace {
+
+// run f(begin, end) over [0, n) on the host cores
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+  unsigned hw = std::thread::hardware_concurrency();
+  int nt = (int)std::max(1u, std::min(hw, 32u));
+  if (n < 4096 || nt == 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    int64_t b = t * chunk, e = std::min(n, b + chunk);
+    if (b >= e) break;
+    th.emplace_back(f, b, e);
+  }
+  for (auto& x : th) x.join();
+}
+
+// Legendre P_{n-1}(x), P_n(x) by the three-term recurrence
+void legendre_pair(int n, double x, double& pnm1, double& pn) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    pnm1 = 0.0;
+    pn = 1.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  pnm1 = p0;
+  pn = p1;
+}
+
+// symmetric eigen-decomposition by cyclic Jacobi rotations: A = Q diag(w) Q^T
+void jacobi_eigen(int n, std::vector<double> A, std::vector<double>& w, std::vector<double>& Q) {
+  Q.assign(n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += A[i * n + j] * A[i * n + j];
+        if (i != j) off += A[i * n + j] * A[i * n + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double apq = A[p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          double akp = A[k * n + p], akq = A[k * n + q];
+          A[k * n + p] = c * akp - s * akq;
+          A[k * n + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          double apk = A[p * n + k], aqk = A[q * n + k];
+          A[p * n + k] = c * apk - s * aqk;
+          A[q * n + k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double qkp = Q[k * n + p], qkq = Q[k * n + q];
+          Q[k * n + p] = c * qkp - s * qkq;
+          Q[k * n + q] = s * qkp + c * qkq;
+        }
+      }
+  }
+  w.resize(n);
+  for (int i = 0; i < n; ++i) w[i] = A[i * n + i];
+  // ascending eigenvalues
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return w[a] < w[b]; });
+  std::vector<double> w2(n), Q2(n * n);
+  for (int c = 0; c < n; ++c) {
+    w2[c] = w[ord[c]];
+    for (int r = 0; r < n; ++r) Q2[r * n + c] = Q[r * n + ord[c]];
+  }
+  w = w2;
+  Q = Q2;
+}
+
+inline int corner_pos(int a, int b, int c) { return a + 2 * b + 4 * c; }
+
+struct EdgeKey {
+  int64_t lo, hi;
+  int64_t e;
+  int le;
+};
+
+struct FaceKey {
+  int64_t v[4];
+  int64_t e;
+  int lf;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// 1D reference data
+// ---------------------------------------------------------------------------
+void build_reference(HostTables& T, int N) {
+  T.N = N;
+  T.n1 = N + 1;
+  T.np = N + 3;
+  const int n1 = N + 1;
+  T.t.assign(n1, 0.0);
+  T.rho.assign(n1, 0.0);
+  T.t[0] = -1.0;
+  T.t[N] = 1.0;
+  const double pi = 3.14159265358979323846;
+  for (int i = 1; i < N; ++i) {
+    // Newton on P_N'(x) = 0 from the Chebyshev-Gauss-Lobatto guess; P_N' and
+    // P_N'' from the recurrence identity and Legendre's equation.
+    double x = -std::cos(pi * i / N);
+    for (int it = 0; it < 100; ++it) {
+      double pm1, p;
+      legendre_pair(N, x, pm1, p);
+      double dp = N * (pm1 - x * p) / (1.0 - x * x);
+      double d2p = (2.0 * x * dp - N * (N + 1.0) * p) / (1.0 - x * x);
+      double dx = dp / d2p;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    T.t[i] = x;
+  }
+  std::vector<double> PN(n1);
+  for (int i = 0; i < n1; ++i) {
+    double pm1, p;
+    legendre_pair(N, T.t[i], pm1, p);
+    PN[i] = p;
+    T.rho[i] = 2.0 / (N * (N + 1.0) * p * p);
+  }
+  // D[i][j] = phi_j'(t_i), closed form for GLL Lagrange interpolants
+  T.D.assign(n1 * n1, 0.0);
+  for (int i = 0; i < n1; ++i)
+    for (int j = 0; j < n1; ++j) {
+      if (i != j)
+        T.D[i * n1 + j] = PN[i] / (PN[j] * (T.t[i] - T.t[j]));
+      else if (i == 0)
+        T.D[i * n1 + j] = -N * (N + 1.0) / 4.0;
+      else if (i == N)
+        T.D[i * n1 + j] = N * (N + 1.0) / 4.0;
+    }
+  // extended pencil (nodes -1..N+1 at positions 0..N+2): element block, plus the
+  // neighbours' two nodes nearest each end vertex; d = D^T diag(rho) D
+  const int np = N + 3;
+  std::vector<double> d(n1 * n1, 0.0);
+  for (int a = 0; a < n1; ++a)
+    for (int b = 0; b < n1; ++b) {
+      double s = 0.0;
+      for (int m = 0; m < n1; ++m) s += T.D[m * n1 + a] * T.D[m * n1 + b] * T.rho[m];
+      d[a * n1 + b] = s;
+    }
+  std::vector<double> K(np * np, 0.0), M(np, 0.0);
+  for (int a = 0; a < n1; ++a) {
+    M[a + 1] += T.rho[a];
+    for (int b = 0; b < n1; ++b) K[(a + 1) * np + (b + 1)] += d[a * n1 + b];
+  }
+  const int L[2] = {N - 1, N};  // left neighbour nodes -> positions 0, 1
+  const int R[2] = {0, 1};      // right neighbour nodes -> positions N+1, N+2
+  for (int a = 0; a < 2; ++a) {
+    M[a] += T.rho[L[a]];
+    M[N + 1 + a] += T.rho[R[a]];
+    for (int b = 0; b < 2; ++b) {
+      K[a * np + b] += d[L[a] * n1 + L[b]];
+      K[(N + 1 + a) * np + (N + 1 + b)] += d[R[a] * n1 + R[b]];
+    }
+  }
+  // K S = M S Lambda, S^T M S = I:  C = M^{-1/2} K M^{-1/2} = Q Lambda Q^T, S = M^{-1/2} Q
+  std::vector<double> C(np * np);
+  for (int a = 0; a < np; ++a)
+    for (int b = 0; b < np; ++b) C[a * np + b] = K[a * np + b] / std::sqrt(M[a] * M[b]);
+  std::vector<double> Q;
+  jacobi_eigen(np, C, T.lam, Q);
+  T.S.assign(np * np, 0.0);
+  for (int a = 0; a < np; ++a)
+    for (int b = 0; b < np; ++b) T.S[a * np + b] = Q[a * np + b] / std::sqrt(M[a]);
+}
+
+// ---------------------------------------------------------------------------
+// numbering
+// ---------------------------------------------------------------------------
+static const int kFaceAxis[6] = {0, 0, 1, 1, 2, 2};
+static const int kFaceSide[6] = {0, 1, 0, 1, 0, 1};
+
+static void tangential(int d, int& t1, int& t2) {
+  t1 = (d == 0) ? 1 : 0;
+  t2 = (d == 2) ? 1 : 2;
+}
+
+int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k) {
+  const int N = T.N;
+  int cx = i == 0 ? 0 : (i == N ? 2 : 1);
+  int cy = j == 0 ? 0 : (j == N ? 2 : 1);
+  int cz = k == 0 ? 0 : (k == N ? 2 : 1);
+  const int32_t* r = &T.rec[((size_t)e * kClasses + cx + 3 * cy + 9 * cz) * kRecInts];
+  int32_t code = r[1];
+  int ai = (int32_t)((uint32_t)code << 22) >> 22;
+  int aj = (int32_t)((uint32_t)code << 12) >> 22;
+  int ak = (int32_t)((uint32_t)code << 2) >> 22;
+  return (int64_t)r[0] + ai * i + aj * j + ak * k;
+}
+
+void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n_vtx) {
+  const int N = T.N, n1 = T.n1;
+  const int64_t E = n_hex;
+  T.E = E;
+  T.n_local = E * n1 * n1 * n1;
+  for (int64_t x = 0; x < E * 8; ++x)
+    if (hex[x] < 0 || hex[x] >= n_vtx) throw Error{SEM_EINVAL, "hexahedron vertex id out of range"};
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < 8; ++a)
+      for (int b = a + 1; b < 8; ++b)
+        if (hex[e * 8 + a] == hex[e * 8 + b]) throw Error{SEM_EMESH, "hexahedron repeats a vertex"};
+
+  // vertices: referenced ids in ascending order
+  std::vector<int64_t> vrank(n_vtx, -1);
+  for (int64_t x = 0; x < E * 8; ++x) vrank[hex[x]] = 0;
+  int64_t V = 0;
+  for (int64_t v = 0; v < n_vtx; ++v)
+    if (vrank[v] == 0) vrank[v] = V++;
+  T.V = V;
+
+  // edges: local edge le = 4 d + 2 b2 + b1 runs along axis d from corner bit 0 to 1
+  std::vector<EdgeKey> ek(E * 12);
+  for (int64_t e = 0; e < E; ++e)
+    for (int d = 0; d < 3; ++d)
+      for (int b2 = 0; b2 < 2; ++b2)
+        for (int b1 = 0; b1 < 2; ++b1) {
+          int t1, t2;
+          tangential(d, t1, t2);
+          int c0[3], c1[3];
+          c0[d] = 0;
+          c0[t1] = b1;
+          c0[t2] = b2;
+          c1[d] = 1;
+          c1[t1] = b1;
+          c1[t2] = b2;
+          int64_t va = hex[e * 8 + corner_pos(c0[0], c0[1], c0[2])];
+          int64_t vb = hex[e * 8 + corner_pos(c1[0], c1[1], c1[2])];
+          int le = 4 * d + 2 * b2 + b1;
+          ek[e * 12 + le] = EdgeKey{std::min(va, vb), std::max(va, vb), e, le};
+        }
+  std::vector<int64_t> edge_rank(E * 12), edge_inc(E * 12);
+  {
+    std::vector<int64_t> ord(E * 12);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+      const EdgeKey &x = ek[a], &y = ek[b];
+      if (x.lo != y.lo) return x.lo < y.lo;
+      if (x.hi != y.hi) return x.hi < y.hi;
+      return x.e < y.e;
+    });
+    int64_t r = -1;
+    T.einc_off.clear();
+    for (int64_t p = 0; p < (int64_t)ord.size(); ++p) {
+      const EdgeKey& x = ek[ord[p]];
+      if (p == 0 || x.lo != ek[ord[p - 1]].lo || x.hi != ek[ord[p - 1]].hi) {
+        ++r;
+        T.einc_off.push_back((int32_t)p);
+      }
+      edge_rank[ord[p]] = r;
+      edge_inc[ord[p]] = p;
+    }
+    T.n_edges = r + 1;
+    T.einc_off.push_back((int32_t)ord.size());
+  }
+
+  // faces: local face lf = 2 d + s, corners listed by (s1 along t1, s2 along t2)
+  std::vector<FaceKey> fk(E * 6);
+  std::vector<int64_t> fv(E * 6 * 4);  // [e][lf][s1 + 2 s2]
+  for (int64_t e = 0; e < E; ++e)
+    for (int lf = 0; lf < 6; ++lf) {
+      int d = kFaceAxis[lf], s = kFaceSide[lf], t1, t2;
+      tangential(d, t1, t2);
+      FaceKey key;
+      for (int s2 = 0; s2 < 2; ++s2)
+        for (int s1 = 0; s1 < 2; ++s1) {
+          int c[3];
+          c[d] = s;
+          c[t1] = s1;
+          c[t2] = s2;
+          int64_t v = hex[e * 8 + corner_pos(c[0], c[1], c[2])];
+          fv[(e * 6 + lf) * 4 + s1 + 2 * s2] = v;
+          key.v[s1 + 2 * s2] = v;
+        }
+      std::sort(key.v, key.v + 4);
+      key.e = e;
+      key.lf = lf;
+      fk[e * 6 + lf] = key;
+    }
+  std::vector<int64_t> face_rank(E * 6);
+  std::vector<int> face_side(E * 6);
+  T.face_nbr.assign(E * 12, -1);
+  {
+    std::vector<int64_t> ord(E * 6);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+      const FaceKey &x = fk[a], &y = fk[b];
+      for (int q = 0; q < 4; ++q)
+        if (x.v[q] != y.v[q]) return x.v[q] < y.v[q];
+      return x.e < y.e;
+    });
+    int64_t r = -1;
+    int side = 0;
+    T.fcount.clear();
+    for (int64_t p = 0; p < (int64_t)ord.size(); ++p) {
+      const FaceKey& x = fk[ord[p]];
+      bool fresh = p == 0 || !std::equal(x.v, x.v + 4, fk[ord[p - 1]].v);
+      if (fresh) {
+        ++r;
+        side = 0;
+        T.fcount.push_back(1);
+      } else {
+        ++side;
+        if (side >= 2) throw Error{SEM_EMESH, "a face is shared by more than two hexahedra"};
+        T.fcount.back() = 2;
+        const FaceKey& y = fk[ord[p - 1]];
+        T.face_nbr[(x.e * 6 + x.lf) * 2 + 0] = (int32_t)y.e;
+        T.face_nbr[(x.e * 6 + x.lf) * 2 + 1] = y.lf;
+        T.face_nbr[(y.e * 6 + y.lf) * 2 + 0] = (int32_t)x.e;
+        T.face_nbr[(y.e * 6 + y.lf) * 2 + 1] = x.lf;
+      }
+      face_rank[ord[p]] = r;
+      face_side[ord[p]] = side;
+    }
+    T.n_faces = r + 1;
+  }
+
+  // vertex incidences, sorted by (vertex, element)
+  std::vector<int64_t> vert_inc(E * 8);
+  {
+    std::vector<int64_t> cnt(V + 1, 0);
+    for (int64_t x = 0; x < E * 8; ++x) cnt[vrank[hex[x]] + 1]++;
+    for (int64_t v = 0; v < V; ++v) cnt[v + 1] += cnt[v];
+    T.vinc_off.assign(cnt.begin(), cnt.end());
+    std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+    for (int64_t e = 0; e < E; ++e)  // element-major sweep keeps elements ascending
+      for (int a = 0; a < 8; ++a) vert_inc[e * 8 + a] = fill[vrank[hex[e * 8 + a]]]++;
+  }
+
+  const int64_t m = N - 1;
+  T.base_e = V;
+  T.base_f = V + T.n_edges * m;
+  T.base_i = T.base_f + T.n_faces * m * m;
+  T.n_global = T.base_i + E * m * m * m;
+  if (T.n_global >= (int64_t)INT32_MAX || T.n_local >= (int64_t)INT32_MAX)
+    throw Error{SEM_EUNSUPPORTED, "mesh too large for 32-bit node ids"};
+  T.wedge_off = 2 * T.n_faces * m * m;
+  T.wvert_off = T.wedge_off + (int64_t)E * 12 * m;
+  T.w_size = T.wvert_off + (int64_t)E * 8;
+
+  // entity records
+  T.rec.assign((size_t)E * kClasses * kRecInts, 0);
+  for (int64_t e = 0; e < E; ++e) {
+    for (int cz = 0; cz < 3; ++cz)
+      for (int cy = 0; cy < 3; ++cy)
+        for (int cx = 0; cx < 3; ++cx) {
+          int cls[3] = {cx, cy, cz};
+          int32_t* r = &T.rec[((size_t)e * kClasses + cx + 3 * cy + 9 * cz) * kRecInts];
+          int nb = (cx != 1) + (cy != 1) + (cz != 1);
+          int64_t gbase = 0, wbase = 0;
+          int coef[3] = {0, 0, 0};
+          int flags = 0;
+          if (nb == 3) {  // vertex
+            int p = corner_pos(cx / 2, cy / 2, cz / 2);
+            gbase = vrank[hex[e * 8 + p]];
+            int64_t inc = vert_inc[e * 8 + p];
+            wbase = T.wvert_off + inc;
+            if (inc == T.vinc_off[gbase]) flags |= kFlagOwned;
+          } else if (nb == 2) {  // edge along the axis whose class is 1
+            int d = cx == 1 ? 0 : (cy == 1 ? 1 : 2);
+            int t1, t2;
+            tangential(d, t1, t2);
+            int le = 4 * d + 2 * (cls[t2] / 2) + (cls[t1] / 2);
+            const EdgeKey& k = ek[e * 12 + le];
+            int c0[3];
+            c0[d] = 0;
+            c0[t1] = cls[t1] / 2;
+            c0[t2] = cls[t2] / 2;
+            int64_t va = hex[e * 8 + corner_pos(c0[0], c0[1], c0[2])];
+            bool fwd = va == k.lo;
+            int64_t ed = edge_rank[e * 12 + le];
+            int64_t inc = edge_inc[e * 12 + le];
+            int64_t g0 = T.base_e + ed * m;
+            if (fwd) {
+              gbase = g0 - 1;
+              coef[d] = 1;
+            } else {
+              gbase = g0 + N - 1;
+              coef[d] = -1;
+            }
+            wbase = gbase - g0 + T.wedge_off + inc * m;
+            if (inc == T.einc_off[ed]) flags |= kFlagOwned;
+          } else if (nb == 1) {  // face normal to the axis whose class is not 1
+            int d = cx != 1 ? 0 : (cy != 1 ? 1 : 2);
+            int s = cls[d] / 2;
+            int lf = 2 * d + s;
+            int t1, t2;
+            tangential(d, t1, t2);
+            const int64_t* f4 = &fv[(e * 6 + lf) * 4];
+            int w0 = (int)(std::min_element(f4, f4 + 4) - f4);
+            int s1_0 = w0 % 2, s2_0 = w0 / 2;
+            int64_t nb1 = f4[(1 - s1_0) + 2 * s2_0], nb2 = f4[s1_0 + 2 * (1 - s2_0)];
+            int sg1 = s1_0 ? -1 : 1, c1 = s1_0 ? N : 0;
+            int sg2 = s2_0 ? -1 : 1, c2 = s2_0 ? N : 0;
+            int64_t f = face_rank[e * 6 + lf];
+            int64_t g0 = T.base_f + f * m * m;
+            if (nb1 < nb2) {  // p along t1
+              coef[t1] = sg1;
+              coef[t2] = (int)m * sg2;
+              gbase = g0 - N + m * c2 + c1;
+            } else {
+              coef[t1] = (int)m * sg1;
+              coef[t2] = sg2;
+              gbase = g0 - N + m * c1 + c2;
+            }
+            int sd = face_side[e * 6 + lf];
+            wbase = gbase - g0 + (2 * f + sd) * m * m;
+            if (sd == 0) flags |= kFlagOwned;
+          } else {  // interior
+            gbase = T.base_i + e * m * m * m - 1 - m - m * m;
+            coef[0] = 1;
+            coef[1] = (int)m;
+            coef[2] = (int)(m * m);
+            wbase = -1;
+            flags |= kFlagOwned | kFlagInterior;
+          }
+          r[0] = (int32_t)gbase;
+          r[1] = pack_coef(coef[0], coef[1], coef[2]);
+          r[2] = (int32_t)wbase;
+          r[3] = flags;
+        }
+  }
+
+  // default Dirichlet set: every node of a face owned by one hexahedron
+  T.dir.assign(T.n_global, 0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int lf = 0; lf < 6; ++lf) {
+      if (T.face_nbr[(e * 6 + lf) * 2] >= 0) continue;
+      int d = kFaceAxis[lf], s = kFaceSide[lf], t1, t2;
+      tangential(d, t1, t2);
+      for (int b = 0; b <= N; ++b)
+        for (int a = 0; a <= N; ++a) {
+          int x[3];
+          x[d] = s * N;
+          x[t1] = a;
+          x[t2] = b;
+          T.dir[gid_of(T, e, x[0], x[1], x[2])] = 1;
+        }
+    }
+
+  // first local copy of every global node
+  T.owner.assign(T.n_global, -1);
+  for (int64_t e = 0; e < E; ++e)
+    for (int k = 0; k <= N; ++k)
+      for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i) {
+          int64_t g = gid_of(T, e, i, j, k);
+          if (T.owner[g] < 0) T.owner[g] = (int32_t)(e * n1 * n1 * n1 + i + n1 * (j + n1 * k));
+        }
+}
+
+void export_l2g(const HostTables& T, int32_t* l2g) {
+  const int n1 = T.n1;
+  parallel_for(T.E, [&](int64_t b, int64_t e1) {
+    for (int64_t e = b; e < e1; ++e)
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i)
+            l2g[e * n1 * n1 * n1 + i + n1 * (j + n1 * k)] = (int32_t)gid_of(T, e, i, j, k);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+void build_geometry(HostTables& T, const double* vtx, const int64_t* hex) {
+  const int N = T.N, n1 = T.n1;
+  const int64_t E = T.E, nn = (int64_t)n1 * n1 * n1;
+  T.G.assign((size_t)E * 6 * nn, 0.0);
+  T.mass.assign((size_t)E * nn, 0.0);
+  T.h.assign((size_t)E * 3, 0.0);
+  std::vector<double> xl((size_t)E * nn * 3);
+  std::vector<int> bad(std::max<unsigned>(1, std::thread::hardware_concurrency()) * 0 + 1, 0);
+  std::vector<char> badel(E, 0);
+  const std::vector<double>& t = T.t;
+  parallel_for(E, [&](int64_t b0, int64_t b1) {
+    for (int64_t e = b0; e < b1; ++e) {
+      double X[8][3];
+      for (int p = 0; p < 8; ++p)
+        for (int r = 0; r < 3; ++r) X[p][r] = vtx[hex[e * 8 + p] * 3 + r];
+      // box sizes: mean length of the four edges parallel to each reference axis
+      for (int d = 0; d < 3; ++d) {
+        double s = 0.0;
+        for (int q = 0; q < 4; ++q) {
+          int u = q & 1, v = q >> 1;
+          int c0[3], c1[3];
+          int t1, t2;
+          tangential(d, t1, t2);
+          c0[d] = 0;
+          c1[d] = 1;
+          c0[t1] = c1[t1] = u;
+          c0[t2] = c1[t2] = v;
+          const double* a = X[corner_pos(c0[0], c0[1], c0[2])];
+          const double* bb = X[corner_pos(c1[0], c1[1], c1[2])];
+          s += std::sqrt((a[0] - bb[0]) * (a[0] - bb[0]) + (a[1] - bb[1]) * (a[1] - bb[1]) +
+                         (a[2] - bb[2]) * (a[2] - bb[2]));
+        }
+        T.h[e * 3 + d] = 0.25 * s;
+      }
+      for (int k = 0; k < n1; ++k)
+        for (int j = 0; j < n1; ++j)
+          for (int i = 0; i < n1; ++i) {
+            const double xi = t[i], eta = t[j], zeta = t[k];
+            const double f[2][3] = {{0.5 * (1 - xi), 0.5 * (1 - eta), 0.5 * (1 - zeta)},
+                                    {0.5 * (1 + xi), 0.5 * (1 + eta), 0.5 * (1 + zeta)}};
+            const double df[2] = {-0.5, 0.5};
+            double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, x[3] = {0, 0, 0};
+            for (int c = 0; c < 2; ++c)
+              for (int bb = 0; bb < 2; ++bb)
+                for (int a = 0; a < 2; ++a) {
+                  const double* P = X[corner_pos(a, bb, c)];
+                  double w0 = df[a] * f[bb][1] * f[c][2];
+                  double w1 = f[a][0] * df[bb] * f[c][2];
+                  double w2 = f[a][0] * f[bb][1] * df[c];
+                  double w3 = f[a][0] * f[bb][1] * f[c][2];
+                  for (int r = 0; r < 3; ++r) {
+                    J[r][0] += P[r] * w0;
+                    J[r][1] += P[r] * w1;
+                    J[r][2] += P[r] * w2;
+                    x[r] += P[r] * w3;
+                  }
+                }
+            double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+            if (!(det > 0.0)) badel[e] = 1;
+            // M = J^T J and its inverse by cofactors
+            double Mt[3][3];
+            for (int a = 0; a < 3; ++a)
+              for (int c = 0; c < 3; ++c) Mt[a][c] = J[0][a] * J[0][c] + J[1][a] * J[1][c] + J[2][a] * J[2][c];
+            double c00 = Mt[1][1] * Mt[2][2] - Mt[1][2] * Mt[2][1];
+            double c01 = Mt[0][2] * Mt[2][1] - Mt[0][1] * Mt[2][2];
+            double c02 = Mt[0][1] * Mt[1][2] - Mt[0][2] * Mt[1][1];
+            double c11 = Mt[0][0] * Mt[2][2] - Mt[0][2] * Mt[2][0];
+            double c12 = Mt[0][2] * Mt[1][0] - Mt[0][0] * Mt[1][2];
+            double c22 = Mt[0][0] * Mt[1][1] - Mt[0][1] * Mt[1][0];
+            double detM = Mt[0][0] * c00 + Mt[0][1] * (Mt[1][2] * Mt[2][0] - Mt[1][0] * Mt[2][2]) +
+                          Mt[0][2] * (Mt[1][0] * Mt[2][1] - Mt[1][1] * Mt[2][0]);
+            double w = T.rho[i] * T.rho[j] * T.rho[k] * det;
+            double sc = w / detM;
+            int64_t node = i + n1 * (j + n1 * k);
+            double* G = &T.G[(size_t)e * 6 * nn];
+            G[0 * nn + node] = sc * c00;
+            G[1 * nn + node] = sc * c01;
+            G[2 * nn + node] = sc * c02;
+            G[3 * nn + node] = sc * c11;
+            G[4 * nn + node] = sc * c12;
+            G[5 * nn + node] = sc * c22;
+            T.mass[e * nn + node] = w;
+            for (int r = 0; r < 3; ++r) xl[(e * nn + node) * 3 + r] = x[r];
+          }
+    }
+  });
+  for (int64_t e = 0; e < E; ++e)
+    if (badel[e]) throw Error{SEM_EMESH, "inverted or degenerate hexahedron (|J| <= 0 at a GLL node)"};
+  // lumped mass: copies summed in ascending local index; coordinates of the first copy
+  T.mN.assign(T.n_global, 0.0);
+  T.xN.assign(T.n_global * 3, 0.0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int k = 0; k <= N; ++k)
+      for (int j = 0; j <= N; ++j)
+        for (int i = 0; i <= N; ++i) {
+          int64_t g = gid_of(T, e, i, j, k);
+          int64_t node = i + n1 * (j + n1 * k);
+          T.mN[g] += T.mass[e * nn + node];
+        }
+  for (int64_t g = 0; g < T.n_global; ++g)
+    for (int r = 0; r < 3; ++r) T.xN[g * 3 + r] = xl[(size_t)T.owner[g] * 3 + r];
+  (void)bad;
+}
+
+// ---------------------------------------------------------------------------
+// overlapping patches
+// ---------------------------------------------------------------------------
+namespace {
+struct FaceMap {
+  int perm[3], sign[3], off[3];
+};
+}  // namespace
+
+void build_patches(HostTables& T, const int64_t* hex) {
+  const int N = T.N, np = T.np;
+  const int64_t E = T.E, pp = (int64_t)np * np * np;
+  // affine maps across every interior face: y[perm[d]] = sign[d] x[d] + off[d]
+  std::vector<FaceMap> fmap(E * 6);
+  auto lattice = [&](int p, int* c) {
+    c[0] = (p & 1) * N;
+    c[1] = ((p >> 1) & 1) * N;
+    c[2] = ((p >> 2) & 1) * N;
+  };
+  for (int64_t e = 0; e < E; ++e)
+    for (int lf = 0; lf < 6; ++lf) {
+      int64_t e2 = T.face_nbr[(e * 6 + lf) * 2];
+      if (e2 < 0) continue;
+      int lf2 = T.face_nbr[(e * 6 + lf) * 2 + 1];
+      int d = kFaceAxis[lf], s = kFaceSide[lf], d2 = kFaceAxis[lf2], s2 = kFaceSide[lf2];
+      FaceMap fm;
+      auto pos_in_e2 = [&](int64_t v) {
+        for (int p = 0; p < 8; ++p)
+          if (hex[e2 * 8 + p] == v) return p;
+        return -1;
+      };
+      int base[3] = {0, 0, 0};
+      base[d] = s;
+      int y0[3];
+      lattice(pos_in_e2(hex[e * 8 + corner_pos(base[0], base[1], base[2])]), y0);
+      int t1, t2;
+      tangential(d, t1, t2);
+      for (int tt : {t1, t2}) {
+        int c1[3] = {base[0], base[1], base[2]};
+        c1[tt] = 1;
+        int y1[3];
+        lattice(pos_in_e2(hex[e * 8 + corner_pos(c1[0], c1[1], c1[2])]), y1);
+        for (int ax = 0; ax < 3; ++ax)
+          if (y1[ax] != y0[ax]) {
+            fm.perm[tt] = ax;
+            fm.sign[tt] = (y1[ax] - y0[ax]) / N;
+            fm.off[tt] = y0[ax];
+          }
+      }
+      fm.perm[d] = d2;
+      fm.sign[d] = (s == s2) ? -1 : 1;
+      fm.off[d] = (s == 0 && s2 == 0) ? 0 : (s == 0 ? N : (s2 == 0 ? -N : 2 * N));
+      fmap[e * 6 + lf] = fm;
+    }
+  auto edge_valence = [&](int64_t va, int64_t vb, int64_t e) {
+    // number of hexahedra sharing mesh edge (va, vb): the incidence list of the
+    // edge is found from element e's own local edge
+    for (int d = 0; d < 3; ++d)
+      for (int b2 = 0; b2 < 2; ++b2)
+        for (int b1 = 0; b1 < 2; ++b1) {
+          int t1, t2;
+          tangential(d, t1, t2);
+          int c0[3], c1[3];
+          c0[d] = 0;
+          c1[d] = 1;
+          c0[t1] = c1[t1] = b1;
+          c0[t2] = c1[t2] = b2;
+          int64_t a = hex[e * 8 + corner_pos(c0[0], c0[1], c0[2])];
+          int64_t b = hex[e * 8 + corner_pos(c1[0], c1[1], c1[2])];
+          if ((a == va && b == vb) || (a == vb && b == va)) {
+            int64_t g = gid_of(T, e, c0[0] * N + (d == 0), c0[1] * N + (d == 1), c0[2] * N + (d == 2));
+            int64_t ed = (g - T.base_e) / (N - 1);
+            return T.einc_off[ed + 1] - T.einc_off[ed];
+          }
+        }
+    return 0;
+  };
+  T.ip.assign((size_t)E * pp, -1);
+  parallel_for(E, [&](int64_t b0, int64_t b1) {
+    for (int64_t s = b0; s < b1; ++s) {
+      for (int c = 0; c < np; ++c)
+        for (int b = 0; b < np; ++b)
+          for (int a = 0; a < np; ++a) {
+            int x[3] = {a - 1, b - 1, c - 1};
+            int nout = 0;
+            int corner[3];
+            for (int d = 0; d < 3; ++d) {
+              bool o = x[d] < 0 || x[d] > N;
+              nout += o;
+              corner[d] = x[d] < 0 ? 0 : 1;
+            }
+            if (nout == 2) {
+              int dfree = (x[0] >= 0 && x[0] <= N) ? 0 : ((x[1] >= 0 && x[1] <= N) ? 1 : 2);
+              int c0[3] = {corner[0], corner[1], corner[2]}, c1[3] = {corner[0], corner[1], corner[2]};
+              c0[dfree] = 0;
+              c1[dfree] = 1;
+              if (edge_valence(hex[s * 8 + corner_pos(c0[0], c0[1], c0[2])],
+                               hex[s * 8 + corner_pos(c1[0], c1[1], c1[2])], s) != 4)
+                continue;
+            } else if (nout == 3) {
+              int64_t v = hex[s * 8 + corner_pos(corner[0], corner[1], corner[2])];
+              int64_t vr = gid_of(T, s, corner[0] * N, corner[1] * N, corner[2] * N);
+              if (T.vinc_off[vr + 1] - T.vinc_off[vr] != 8) continue;
+              bool ok = true;
+              for (int d = 0; d < 3; ++d) {
+                int c1[3] = {corner[0], corner[1], corner[2]};
+                c1[d] = 1 - c1[d];
+                if (edge_valence(v, hex[s * 8 + corner_pos(c1[0], c1[1], c1[2])], s) != 4) ok = false;
+              }
+              if (!ok) continue;
+            }
+            int64_t e = s;
+            bool valid = true;
+            for (int step = 0; step < 4; ++step) {
+              int d = -1;
+              for (int q = 0; q < 3; ++q)
+                if (x[q] < 0 || x[q] > N) {
+                  d = q;
+                  break;
+                }
+              if (d < 0) break;
+              int lf = 2 * d + (x[d] < 0 ? 0 : 1);
+              int64_t e2 = T.face_nbr[(e * 6 + lf) * 2];
+              if (e2 < 0) {
+                valid = false;
+                break;
+              }
+              const FaceMap& fm = fmap[e * 6 + lf];
+              int y[3];
+              for (int q = 0; q < 3; ++q) y[fm.perm[q]] = fm.sign[q] * x[q] + fm.off[q];
+              x[0] = y[0];
+              x[1] = y[1];
+              x[2] = y[2];
+              e = e2;
+            }
+            if (valid) T.ip[(size_t)s * pp + a + np * (b + np * c)] = (int32_t)gid_of(T, e, x[0], x[1], x[2]);
+          }
+    }
+  });
+  // inverse table: for every global node, the patch slots that hold it, ascending
+  T.ip_off.assign(T.n_global + 1, 0);
+  for (size_t x = 0; x < T.ip.size(); ++x)
+    if (T.ip[x] >= 0) T.ip_off[T.ip[x] + 1]++;
+  for (int64_t g = 0; g < T.n_global; ++g) T.ip_off[g + 1] += T.ip_off[g];
+  if ((int64_t)T.ip.size() >= (int64_t)INT32_MAX) throw Error{SEM_EUNSUPPORTED, "patch table too large"};
+  T.ip_slot.assign(T.ip_off[T.n_global], 0);
+  std::vector<int32_t> fill(T.ip_off.begin(), T.ip_off.end() - 1);
+  for (size_t x = 0; x < T.ip.size(); ++x)
+    if (T.ip[x] >= 0) T.ip_slot[fill[T.ip[x]]++] = (int32_t)x;
+}
+
+// ---------------------------------------------------------------------------
+// coarse space: order-1 operator on the free vertices, BFS levels
+// ---------------------------------------------------------------------------
+void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex) {
+  const int64_t E = T.E;
+  // element matrices of the order-1 operator: quadrature at the 8 corners (weights 1)
+  T.corner_K.assign((size_t)E * 64, 0.0);
+  parallel_for(E, [&](int64_t b0, int64_t b1) {
+    for (int64_t e = b0; e < b1; ++e) {
+      double X[8][3];
+      for (int p = 0; p < 8; ++p)
+        for (int r = 0; r < 3; ++r) X[p][r] = vtx[hex[e * 8 + p] * 3 + r];
+      double* K = &T.corner_K[e * 64];
+      for (int q = 0; q < 8; ++q) {
+        int qa = q & 1, qb = (q >> 1) & 1, qc = q >> 2;
+        double J[3][3];
+        for (int r = 0; r < 3; ++r) {
+          J[r][0] = 0.5 * (X[corner_pos(1, qb, qc)][r] - X[corner_pos(0, qb, qc)][r]);
+          J[r][1] = 0.5 * (X[corner_pos(qa, 1, qc)][r] - X[corner_pos(qa, 0, qc)][r]);
+          J[r][2] = 0.5 * (X[corner_pos(qa, qb, 1)][r] - X[corner_pos(qa, qb, 0)][r]);
+        }
+        double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                     J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                     J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        // inverse Jacobian by cofactors: Jinv[a][r]
+        double Ji[3][3];
+        Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
+        Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / det;
+        Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / det;
+        Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / det;
+        Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / det;
+        Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / det;
+        Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / det;
+        Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / det;
+        Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / det;
+        // physical gradient of each corner basis function at corner q
+        double gphys[8][3];
+        for (int p = 0; p < 8; ++p) {
+          int pa = p & 1, pb = (p >> 1) & 1, pc = p >> 2;
+          double gr[3];
+          gr[0] = (pb == qb && pc == qc) ? (pa ? 0.5 : -0.5) : 0.0;
+          gr[1] = (pa == qa && pc == qc) ? (pb ? 0.5 : -0.5) : 0.0;
+          gr[2] = (pa == qa && pb == qb) ? (pc ? 0.5 : -0.5) : 0.0;
+          for (int r = 0; r < 3; ++r) gphys[p][r] = Ji[0][r] * gr[0] + Ji[1][r] * gr[1] + Ji[2][r] * gr[2];
+        }
+        for (int a = 0; a < 8; ++a)
+          for (int b = 0; b < 8; ++b)
+            K[a * 8 + b] += det * (gphys[a][0] * gphys[b][0] + gphys[a][1] * gphys[b][1] +
+                                   gphys[a][2] * gphys[b][2]);
+      }
+    }
+  });
+}
+
+void build_coarse_levels(HostTables& T) {
+  const int N = T.N;
+  const int64_t E = T.E, V = T.V;
+  // free vertices and their adjacency
+  std::vector<int64_t> vid(E * 8);
+  for (int64_t e = 0; e < E; ++e)
+    for (int p = 0; p < 8; ++p) vid[e * 8 + p] = gid_of(T, e, (p & 1) * N, ((p >> 1) & 1) * N, (p >> 2) * N);
+  std::vector<std::vector<int64_t>> adj(V);
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < 8; ++a)
+      for (int b = 0; b < 8; ++b)
+        if (a != b) adj[vid[e * 8 + a]].push_back(vid[e * 8 + b]);
+  for (auto& l : adj) {
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+  }
+  std::vector<char> freev(V);
+  for (int64_t v = 0; v < V; ++v) freev[v] = T.dir[v] == 0;
+  // coordinates of the vertex nodes, longest extent of the mesh
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < V; ++v)
+    for (int r = 0; r < 3; ++r) {
+      lo[r] = std::min(lo[r], T.xN[v * 3 + r]);
+      hi[r] = std::max(hi[r], T.xN[v * 3 + r]);
+    }
+  int ax = 0;
+  for (int r = 1; r < 3; ++r)
+    if (hi[r] - lo[r] > hi[ax] - lo[ax]) ax = r;
+  double hmean = 0.0;
+  for (int64_t e = 0; e < E; ++e) hmean += T.h[e * 3 + ax];
+  hmean /= std::max<int64_t>(1, E);
+  // multi-source BFS from the free vertices nearest the low end of that axis
+  std::vector<int32_t> level(V, -1);
+  std::vector<int64_t> order;
+  order.reserve(V);
+  std::vector<int64_t> lvl_start;
+  int64_t nfree = 0;
+  for (int64_t v = 0; v < V; ++v) nfree += freev[v];
+  int cur = 0;
+  while ((int64_t)order.size() < nfree) {
+    double xmin = 1e300;
+    for (int64_t v = 0; v < V; ++v)
+      if (freev[v] && level[v] < 0) xmin = std::min(xmin, T.xN[v * 3 + ax]);
+    std::vector<int64_t> front;
+    for (int64_t v = 0; v < V; ++v)
+      if (freev[v] && level[v] < 0 && T.xN[v * 3 + ax] <= xmin + 0.5 * hmean) front.push_back(v);
+    while (!front.empty()) {
+      lvl_start.push_back((int64_t)order.size());
+      for (int64_t v : front) level[v] = cur;
+      std::sort(front.begin(), front.end());
+      for (int64_t v : front) order.push_back(v);
+      std::vector<int64_t> next;
+      for (int64_t v : front)
+        for (int64_t w : adj[v])
+          if (freev[w] && level[w] < 0) {
+            level[w] = cur + 1;
+            next.push_back(w);
+          }
+      std::sort(next.begin(), next.end());
+      next.erase(std::unique(next.begin(), next.end()), next.end());
+      ++cur;
+      front.swap(next);
+    }
+  }
+  lvl_start.push_back((int64_t)order.size());
+  T.nc = (int64_t)order.size();
+  T.cidx.assign(V, -1);
+  for (int64_t p = 0; p < T.nc; ++p) T.cidx[order[p]] = (int32_t)p;
+  T.levels.clear();
+  int64_t pool = 0;
+  for (size_t l = 0; l + 1 < lvl_start.size(); ++l) {
+    Level L;
+    L.off = lvl_start[l];
+    L.size = lvl_start[l + 1] - lvl_start[l];
+    L.sinv = pool;
+    pool += L.size * L.size;
+    T.levels.push_back(L);
+  }
+  // CSR of A_c in level order (assembled from the corner matrices, element order)
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(T.nc);
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < 8; ++a) {
+      int32_t ra = T.cidx[vid[e * 8 + a]];
+      if (ra < 0) continue;
+      for (int b = 0; b < 8; ++b) {
+        int32_t cb = T.cidx[vid[e * 8 + b]];
+        if (cb < 0) continue;
+        rows[ra].push_back({cb, T.corner_K[e * 64 + a * 8 + b]});
+      }
+    }
+  T.ac_off.assign(T.nc + 1, 0);
+  T.ac_col.clear();
+  T.ac_val.clear();
+  for (int64_t r = 0; r < T.nc; ++r) {
+    auto& l = rows[r];
+    std::stable_sort(l.begin(), l.end(), [](auto& x, auto& y) { return x.first < y.first; });
+    for (size_t q = 0; q < l.size(); ++q) {
+      if (q > 0 && l[q].first == l[q - 1].first)
+        T.ac_val.back() += l[q].second;
+      else {
+        T.ac_col.push_back(l[q].first);
+        T.ac_val.push_back(l[q].second);
+      }
+    }
+    T.ac_off[r + 1] = (int32_t)T.ac_col.size();
+  }
+}
+
+}  // namespace sem

@@ -1,0 +1,279 @@
+"""ctypes binding of ``libsem.so`` (argument marshalling only).
+
+Every computation happens in the C/HIP library.  Device vectors are torch
+tensors on a HIP device; they are passed as raw pointers together with
+torch's current stream.  The module raises at import time when the library
+has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1506_05996_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+SEM_OK, SEM_EINVAL, SEM_ENOMEM, SEM_EMESH, SEM_ENOCONV, SEM_EBREAKDOWN, SEM_EHIP, SEM_EUNSUPPORTED = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+SEM_F64, SEM_F32 = 0, 1
+PC_NONE, PC_FINE, PC_COARSE, PC_TWOSCALE = 0, 1, 2, 3
+SOLVE_FP64, SOLVE_FP32_REFINED = 0, 1
+
+STATUS_NAMES = {0: "SEM_OK", -1: "SEM_EINVAL", -2: "SEM_ENOMEM", -3: "SEM_EMESH", -4: "SEM_ENOCONV",
+                -5: "SEM_EBREAKDOWN", -6: "SEM_EHIP", -7: "SEM_EUNSUPPORTED"}
+
+# every symbol declared in include/sem.h
+EXPORTS = [
+    "sem_default_setup_opts", "sem_default_solve_opts", "sem_mesh_setup", "sem_mesh_destroy",
+    "sem_mesh_sizes", "sem_mesh_numbering", "sem_mesh_gs_csr", "sem_mesh_patch_table",
+    "sem_mesh_node_coords", "sem_mesh_lumped_mass", "sem_mesh_boundary_mask", "sem_mesh_geometry",
+    "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
+    "sem_last_error",
+]
+
+
+class SetupOpts(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("host_only", ctypes.c_int), ("build_fp32", ctypes.c_int)]
+
+
+class SolveOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("pc", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("use_x0", ctypes.c_int), ("inner_rtol", ctypes.c_double),
+                ("max_outer", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("outer_iterations", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_cap", ctypes.c_int),
+                ("history_len", ctypes.c_int)]
+
+
+_p = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_lib.sem_default_setup_opts.argtypes = [ctypes.POINTER(SetupOpts)]
+_lib.sem_default_setup_opts.restype = None
+_lib.sem_default_solve_opts.argtypes = [ctypes.POINTER(SolveOpts)]
+_lib.sem_default_solve_opts.restype = None
+_lib.sem_mesh_setup.argtypes = [_p, _i64, _p, _i64, ctypes.c_int, ctypes.POINTER(SetupOpts), ctypes.POINTER(_p)]
+_lib.sem_mesh_destroy.argtypes = [_p]
+_lib.sem_mesh_sizes.argtypes = [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
+for name in ["sem_mesh_numbering", "sem_mesh_patch_table", "sem_mesh_node_coords", "sem_mesh_lumped_mass",
+             "sem_mesh_boundary_mask", "sem_mesh_set_dirichlet"]:
+    getattr(_lib, name).argtypes = [_p, _p]
+_lib.sem_mesh_gs_csr.argtypes = [_p, _p, _p]
+_lib.sem_mesh_geometry.argtypes = [_p, _p, _p]
+_lib.sem_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, _p]
+_lib.sem_precond.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p]
+_lib.sem_coarse_solve.argtypes = [_p, _p, _p, _p]
+_lib.sem_pcg_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
+_lib.sem_last_error.restype = ctypes.c_char_p
+for name in EXPORTS:
+    fn = getattr(_lib, name)
+    if fn.restype is None and name not in ("sem_default_setup_opts", "sem_default_solve_opts"):
+        pass
+
+
+class SemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def last_error() -> str:
+    return _lib.sem_last_error().decode()
+
+
+def _check(status):
+    if status != SEM_OK:
+        raise SemError(status, last_error())
+    return status
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def default_solve_opts(**kw) -> SolveOpts:
+    o = SolveOpts()
+    _lib.sem_default_solve_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Mesh:
+    """Owning wrapper of a ``sem_mesh`` handle."""
+
+    def __init__(self, vtx, hexes, order, host_only=False, device=0, build_fp32=True):
+        vtx = np.ascontiguousarray(vtx, dtype=np.float64)
+        hexes = np.ascontiguousarray(hexes, dtype=np.int64)
+        if vtx.ndim != 2 or vtx.shape[1] != 3 or hexes.ndim != 2 or hexes.shape[1] != 8:
+            raise ValueError("vtx must be [V,3] and hexes [E,8]")
+        opts = SetupOpts(device=device, host_only=int(host_only), build_fp32=int(build_fp32))
+        h = ctypes.c_void_p()
+        _check(_lib.sem_mesh_setup(_ptr(vtx), vtx.shape[0], _ptr(hexes), hexes.shape[0], int(order),
+                                   ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+        self.order = int(order)
+        self.n_elem = hexes.shape[0]
+        ng, nl, nv = _i64(), _i64(), _i64()
+        _check(_lib.sem_mesh_sizes(h, ctypes.byref(ng), ctypes.byref(nl), ctypes.byref(nv)))
+        self.n_global, self.n_local, self.n_vertices = ng.value, nl.value, nv.value
+        self.host_only = host_only
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.sem_mesh_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    # --- host tables -------------------------------------------------------
+    def numbering(self) -> np.ndarray:
+        n1 = self.order + 1
+        out = np.empty((self.n_elem, n1, n1, n1), dtype=np.int32)
+        _check(_lib.sem_mesh_numbering(self._h, _ptr(out)))
+        return out
+
+    def gs_csr(self):
+        off = np.empty(self.n_global + 1, dtype=np.int64)
+        idx = np.empty(self.n_local, dtype=np.int32)
+        _check(_lib.sem_mesh_gs_csr(self._h, _ptr(off), _ptr(idx)))
+        return off, idx
+
+    def patch_table(self) -> np.ndarray:
+        m = self.order + 3
+        out = np.empty((self.n_elem, m, m, m), dtype=np.int32)
+        _check(_lib.sem_mesh_patch_table(self._h, _ptr(out)))
+        return out
+
+    def node_coords(self) -> np.ndarray:
+        out = np.empty((self.n_global, 3))
+        _check(_lib.sem_mesh_node_coords(self._h, _ptr(out)))
+        return out
+
+    def lumped_mass(self) -> np.ndarray:
+        out = np.empty(self.n_global)
+        _check(_lib.sem_mesh_lumped_mass(self._h, _ptr(out)))
+        return out
+
+    def boundary_mask(self) -> np.ndarray:
+        out = np.empty(self.n_global, dtype=np.uint8)
+        _check(_lib.sem_mesh_boundary_mask(self._h, _ptr(out)))
+        return out
+
+    def geometry(self):
+        n1 = self.order + 1
+        G = np.empty((self.n_elem, 6, n1, n1, n1))
+        mass = np.empty((self.n_elem, n1, n1, n1))
+        _check(_lib.sem_mesh_geometry(self._h, _ptr(G), _ptr(mass)))
+        return G, mass
+
+    def set_dirichlet(self, mask):
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert mask.shape == (self.n_global,)
+        _check(_lib.sem_mesh_set_dirichlet(self._h, _ptr(mask)))
+
+    # --- device calls ------------------------------------------------------
+    @staticmethod
+    def _dtype_code(t):
+        import torch
+        if t.dtype == torch.float64:
+            return SEM_F64
+        if t.dtype == torch.float32:
+            return SEM_F32
+        raise TypeError("vectors must be float64 or float32")
+
+    def _check_vec(self, t, n=None):
+        import torch
+        n = self.n_global if n is None else n
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"expected a contiguous device tensor of {n} entries")
+
+    def apply_A(self, u, y=None, stream=None):
+        import torch
+        self._check_vec(u)
+        if y is None:
+            y = torch.empty_like(u)
+        self._check_vec(y)
+        if y.dtype != u.dtype:
+            raise TypeError("u and y must share a dtype")
+        _check(_lib.sem_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), _stream(stream)))
+        return y
+
+    def precond(self, r, z=None, pc=PC_TWOSCALE, stream=None):
+        import torch
+        self._check_vec(r)
+        if z is None:
+            z = torch.empty_like(r)
+        self._check_vec(z)
+        _check(_lib.sem_precond(self._h, _dptr(r), _dptr(z), self._dtype_code(r), int(pc), _stream(stream)))
+        return z
+
+    def coarse_solve(self, R, Z=None, stream=None):
+        import torch
+        self._check_vec(R, self.n_vertices)
+        if Z is None:
+            Z = torch.empty_like(R)
+        _check(_lib.sem_coarse_solve(self._h, _dptr(R), _dptr(Z), _stream(stream)))
+        return Z
+
+    def solve(self, b, x=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-8, max_iter=1000, inner_rtol=1e-3,
+              max_outer=20, check_every=1, use_x0=False, history=0, stream=None, raise_on_noconv=True):
+        import torch
+        self._check_vec(b)
+        if b.dtype != torch.float64:
+            raise TypeError("b must be float64")
+        if x is None:
+            x = torch.zeros_like(b)
+        opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
+                                  max_outer=max_outer, check_every=check_every, use_x0=int(use_x0))
+        st = SolveStats()
+        hist = None
+        if history:
+            hist = (ctypes.c_double * history)()
+            st.history = hist
+            st.history_cap = history
+        status = _lib.sem_pcg_solve(self._h, _dptr(b), _dptr(x), ctypes.byref(opts), ctypes.byref(st),
+                                    _stream(stream))
+        info = dict(status=status, iterations=st.iterations, outer=st.outer_iterations,
+                    rel_residual=st.rel_residual, solve_ms=st.solve_ms,
+                    history=list(hist[:st.history_len]) if hist is not None else None)
+        if status != SEM_OK and (status != SEM_ENOCONV or raise_on_noconv):
+            raise SemError(status, last_error() + f" ({info})")
+        return x, info
+
+
+def library_symbols():
+    """Names of the C-ABI symbols the loaded library exports (for checks)."""
+    out = {}
+    for name in EXPORTS:
+        try:
+            out[name] = getattr(_lib, name) is not None
+        except AttributeError:
+            out[name] = False
+    return out

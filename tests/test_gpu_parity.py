@@ -1,0 +1,157 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances: FP64 operator and preconditioner 1e-12 relative L2; FP64 solution
+1e-10; integer tables bit-exact (covered on the host side).
+"""
+import numpy as np
+import pytest
+
+import meshgen
+from oracle.problem import Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = [
+    # name, mesh kwargs, order, rotate/permute
+    ("cube4_N4", dict(k=4, perturb=0.10), 4, False),
+    ("rot3_N3", dict(k=3, perturb=0.10), 3, True),
+    ("rot3_N2", dict(k=3, perturb=0.15), 2, True),
+    ("box_N5", dict(k=(3, 2, 5), perturb=0.1, lengths=(1, 1, 8)), 5, True),
+    ("rot2_N6", dict(k=2, perturb=0.1), 6, True),
+    ("rot3_N7", dict(k=3, perturb=0.15), 7, True),
+    ("rot2_N8", dict(k=(2, 3, 2), perturb=0.1), 8, True),
+    ("rot2_N11", dict(k=2, perturb=0.1), 11, True),
+    ("one_N15", dict(k=(2, 1, 1), perturb=0.0), 15, True),
+]
+
+
+@pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
+def case(request):
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    name, kw, N, rot = request.param
+    print(f"[case] {name}", flush=True)
+    m = meshgen.cube_mesh(**kw)
+    if rot:
+        m, _ = meshgen.rotate_elements(m, seed=41)
+        m, _ = meshgen.permute_elements(m, seed=42)
+    M = sem.Mesh(m.vtx, m.hex, N)
+    P = Problem(m.vtx, m.hex, N)
+    return dict(m=m, M=M, P=P, dev=dev, sem=sem)
+
+
+def test_apply_A_fp64(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-1, 1, M.n_global)
+    y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
+    assert rel_l2(y, P.A(u)) <= 1e-12
+    # manufactured interpolant (smooth field)
+    us = meshgen.manufactured_u(P.x, case["m"].lengths)
+    ys = M.apply_A(torch.tensor(us, device=dev)).cpu().numpy()
+    assert rel_l2(ys, P.A(us)) <= 1e-12
+
+
+def test_apply_A_deterministic(case):
+    M, dev = case["M"], case["dev"]
+    u = torch.tensor(np.random.default_rng(8).uniform(-1, 1, M.n_global), device=dev)
+    y1 = M.apply_A(u)
+    y2 = M.apply_A(u)
+    assert torch.equal(y1, y2)
+
+
+def test_apply_A_fp32(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    u = np.random.default_rng(9).uniform(-1, 1, M.n_global)
+    y = M.apply_A(torch.tensor(u, device=dev, dtype=torch.float32)).double().cpu().numpy()
+    err = rel_l2(y, P.A(u))
+    print(f"fp32 Ax rel err {err:.2e}")
+    assert err <= 5e-6
+
+
+@pytest.mark.parametrize("pc", [3, 1, 2])
+def test_precond_fp64(case, pc):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    r = np.random.default_rng(10).uniform(-1, 1, M.n_global)
+    r[P.num.dirichlet.astype(bool)] = 0.0
+    z = M.precond(torch.tensor(r, device=dev), pc=pc).cpu().numpy()
+    ref = P.precond(fine=bool(pc & 1), coarse=bool(pc & 2))(r)
+    assert rel_l2(z, ref) <= 1e-12
+
+
+def test_precond_fp32(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    r = np.random.default_rng(11).uniform(-1, 1, M.n_global)
+    r[P.num.dirichlet.astype(bool)] = 0.0
+    z = M.precond(torch.tensor(r, device=dev, dtype=torch.float32)).double().cpu().numpy()
+    err = rel_l2(z, P.precond()(r))
+    print(f"fp32 precond rel err {err:.2e}")
+    assert err <= 1e-5
+
+
+def test_coarse_solve(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    C = P.coarse
+    R = np.random.default_rng(12).uniform(-1, 1, M.n_vertices)
+    Z = M.coarse_solve(torch.tensor(R, device=dev)).cpu().numpy()
+    assert rel_l2(Z, C.solve(R)) <= 1e-12
+
+
+def test_pcg_fp64_matches_oracle(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    b = P.load(lambda x: meshgen.manufactured_s(x, case["m"].lengths))
+    ur, it_ref, hist, _ = P.solve(b, rtol=1e-8)
+    x, info = M.solve(torch.tensor(b, device=dev), rtol=1e-8)
+    # same preconditioner, same Krylov iteration: same count, same iterate
+    assert abs(info["iterations"] - it_ref) <= 1
+    x = x.cpu().numpy()
+    assert rel_l2(x, ur) <= 1e-7
+    # both solved tight: the unique discrete solution
+    ut, _, _, _ = P.solve(b, rtol=1e-13)
+    xt, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    assert rel_l2(xt.cpu().numpy(), ut) <= 1e-10
+
+
+def test_pcg_refined(case):
+    M, P, dev = case["M"], case["P"], case["dev"]
+    sem = case["sem"]
+    b = P.load(lambda x: meshgen.manufactured_s(x, case["m"].lengths))
+    x, info = M.solve(torch.tensor(b, device=dev), mode=sem.SOLVE_FP32_REFINED, rtol=1e-10, inner_rtol=1e-3)
+    x = x.cpu().numpy()
+    true_res = np.linalg.norm(b - P.A(x)) / np.linalg.norm(b)
+    print(f"refined: outer {info['outer']} inner {info['iterations']} true res {true_res:.2e}")
+    assert true_res <= 1.5e-10
+    ut, _, _, _ = P.solve(b, rtol=1e-13)
+    assert rel_l2(x, ut) <= 1e-8
+
+
+def test_solve_edge_cases():
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(2, perturb=0.1)
+    M = sem.Mesh(m.vtx, m.hex, 3)
+    b0 = torch.zeros(M.n_global, dtype=torch.float64, device=dev)
+    x, info = M.solve(b0)
+    assert info["iterations"] == 0 and not x.any()
+    P = Problem(m.vtx, m.hex, 3)
+    b = torch.tensor(P.load(meshgen.manufactured_s), device=dev)
+    x, info = M.solve(b, max_iter=1, raise_on_noconv=False)
+    assert info["status"] == sem.SEM_ENOCONV and info["iterations"] == 1
+    bn = b.clone()
+    bn[5] = float("nan")
+    with pytest.raises(sem.SemError) as e:
+        M.solve(bn)
+    assert e.value.status == sem.SEM_EBREAKDOWN
