@@ -1,0 +1,195 @@
+"""Benchmark of the MI355X spectral-element Poisson solver (one GPU).
+
+Workload (default): unit cube split into 56^3 trilinear hexahedra, interior
+vertices perturbed by +-15% of h (seed 1506), element ids randomly permuted,
+order N = 7 (60,698,457 global nodes), manufactured right-hand side of
+u = sin(pi x) sin(pi y) sin(pi z), homogeneous Dirichlet boundary.
+
+Timed region: `--steps` back-to-back FP64 operator applications y = A u
+(element kernel + shared-node gather) with every input resident in HBM,
+bracketed by device synchronisations; HIP events around each kernel on the
+launch stream give the per-kernel durations used for the roofline entry.
+After the timed region, time-to-tolerance of the PCG solve (||b - A x|| /
+||b|| <= 1e-10) is measured in plain FP64 and in the FP32-refined form.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
+METRIC = "Ax GDOF/s + PCG time-to-1e-10 residual, FP32-refined vs FP64, N=7"
+COUNTERS = os.path.join(ROOT, "profiles", "ax_cube56_N7_counters.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1506_05996_amd", "csrc", "sem_kernels.h")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes_ax(n_local, n_global, s=8):
+    """Bytes the operator must move with stored geometry: six G factors and a
+    32-bit index per local node, the input and output global vectors once."""
+    return n_local * (6 * s + 4) + 2 * s * n_global
+
+
+def traffic_from_counters(n_launch_kernels=("ax_kernel", "gs_kernel")):
+    """HBM bytes per apply from committed rocprofv3 counter runs, when they
+    were taken on the current kernel source; else None."""
+    if not os.path.exists(COUNTERS):
+        return None
+    with open(COUNTERS) as f:
+        c = json.load(f)
+    if c.get("kernel_hash") != kernel_hash():
+        return None
+    return c.get("bytes_per_apply")
+
+
+def cpu_baseline(mesh, N, n_global, budget_s=10.0, sample_elems=4096):
+    """The FP64 oracle's operator, timed on the host on a sample of the
+    workload's elements; scaled to GDOF/s of the full workload."""
+    import numpy as np
+
+    from oracle.problem import Problem
+
+    S = min(sample_elems, mesh.n_elem)
+    P = Problem(mesh.vtx, mesh.hex[:S], N, fine=False, coarse=False)
+    u = np.random.default_rng(1507).uniform(-1, 1, P.num.n_global)
+    P.A(u)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        P.A(u)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    t = el / reps
+    t_full = t * mesh.n_elem / S
+    return {"value": n_global / t_full / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle apply_A on the first {S} of {mesh.n_elem} elements of the same mesh "
+                      f"(N={N}), {reps} reps in {el:.1f} s, {t * 1e3:.1f} ms/apply, scaled by elements"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="cube56_N7")
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pcg-reps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    mesh, N = meshgen.workload_mesh(args.workload)
+    lengths = mesh.lengths
+    log(f"[bench] mesh {args.workload}: {mesh.n_elem} hexes, N={N} ({time.time() - t0:.1f} s)")
+    t0 = time.time()
+    M = sem.Mesh(mesh.vtx, mesh.hex, N)
+    setup_s = time.time() - t0
+    log(f"[bench] setup: n_global={M.n_global} n_local={M.n_local} in {setup_s:.1f} s")
+    ng, nl = M.n_global, M.n_local
+
+    u = torch.tensor(np.random.default_rng(1506).uniform(-1, 1, ng), device=dev)
+    y = torch.empty_like(u)
+    for _ in range(args.warmup):
+        M.apply_A(u, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_elem, ms_gs = M.time_apply_A(u, y, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall / args.steps * 1e3
+    value = ng / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] Ax: {ms_per_step:.3f} ms/apply wall, kernels {ms_elem:.3f} + {ms_gs:.3f} ms")
+
+    balg = algorithmic_bytes_ax(nl, ng)
+    t_k = (ms_elem + ms_gs) * 1e-3
+    achieved = balg / t_k / 1e9
+    traffic = traffic_from_counters()
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "sem_apply_A = ax_kernel + gs_kernel",
+                "ms_ax_kernel": round(ms_elem, 4), "ms_gs_kernel": round(ms_gs, 4),
+                "algorithmic_bytes": balg}
+
+    pcg = None
+    if not args.no_pcg:
+        m_n = M.lumped_mass()
+        x_n = M.node_coords()
+        mask = M.boundary_mask().astype(bool)
+        bh = m_n * meshgen.manufactured_s(x_n, lengths)
+        bh[mask] = 0.0
+        ue = meshgen.manufactured_u(x_n, lengths)
+        ue[mask] = 0.0
+        del x_n
+        b = torch.tensor(bh, device=dev)
+        ue_d = torch.tensor(ue, device=dev)
+        mN = torch.tensor(m_n, device=dev)
+        pcg = {}
+        for name, mode in (("fp64", sem.SOLVE_FP64), ("fp32_refined", sem.SOLVE_FP32_REFINED)):
+            times, info = [], None
+            for _ in range(args.pcg_reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = M.solve(b, mode=mode, rtol=1e-10, max_iter=2000, inner_rtol=1e-2, max_outer=40)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+            # true residual in FP64 and error against the exact solution
+            r = b - M.apply_A(x)
+            res = float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b))
+            err = x - ue_d
+            emax = float(err.abs().max())
+            el2 = float(torch.sqrt((mN * err * err).sum()))
+            pcg[name] = {"time_s": round(float(np.median(times)), 4), "iterations": info["iterations"],
+                         "outer": info["outer"], "true_rel_residual": res, "err_max_vs_exact": emax,
+                         "err_l2m_vs_exact": el2}
+            log(f"[bench] PCG {name}: {pcg[name]}")
+        pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
+        del b, ue_d, mN
+
+    cpu = None
+    if not args.no_cpu:
+        log("[bench] CPU baseline (oracle) ...")
+        cpu = cpu_baseline(mesh, N, ng)
+        log(f"[bench] CPU baseline: {cpu}")
+
+    out = {"metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "hexes": mesh.n_elem, "order": N, "n_global": ng,
+                      "perturbation": mesh.meta.get("perturb"), "seed": 1506, "step": "one FP64 apply of A",
+                      "setup_s": round(setup_s, 2)},
+           "roofline": roofline, "pcg": pcg, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -176,6 +176,16 @@ int sem_coarse_solve(sem_mesh m, const double* R_dev, double* Z_dev, void* strea
 int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solve_opts* o,
                   sem_solve_stats* st, void* stream);
 
+/*
+ * sem_time_apply_A -- run `reps` applications of sem_apply_A back to back on
+ * `stream` with HIP events recorded around each of its two kernels (element
+ * kernel, shared-node gather), synchronise, and return the mean duration of
+ * each kernel in milliseconds.  Same arguments and errors as sem_apply_A;
+ * reps >= 1.  For measurement and tuning.
+ */
+int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int reps, void* stream,
+                     double* ms_element, double* ms_gather);
+
 const char* sem_last_error(void);
 
 #ifdef __cplusplus

@@ -80,7 +80,7 @@ struct sem_mesh_s {
   DBuf<double> S64, lam64, h64, zP64;
   DBuf<float> S32, lam32, h32, zP32;
   // coarse
-  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Zv, sinv, ac_val;
+  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Ylev, Zv, sinv, ac_val;
   DBuf<int32_t> ac_off, ac_col;
   // PCG work
   DBuf<double> v64[5];
@@ -147,14 +147,20 @@ void launch_ax(sem_mesh m, const T* u, T* y, hipStream_t s) {
   hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
                      Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, T_.E);
   SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void launch_gs(sem_mesh m, T* y, hipStream_t s) {
+  const HostTables& T_ = m->T;
   hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)blocks_for(T_.base_i)), dim3(kGS), 0, s, y, Wp<T>(m),
                      m->vinc_off.p, m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1,
                      T_.wedge_off, T_.wvert_off);
   SEM_HIP(hipGetLastError());
 }
 
+// element kernel only (the gather follows separately)
 template <typename T>
-void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
+void apply_A_elements(sem_mesh m, const T* u, T* y, hipStream_t s) {
   switch (m->T.N) {
 #define CASE(NN) \
   case NN:       \
@@ -166,6 +172,12 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
     default:
       throw Error{SEM_EUNSUPPORTED, "order not compiled"};
   }
+}
+
+template <typename T>
+void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
+  apply_A_elements<T>(m, u, y, s);
+  launch_gs<T>(m, y, s);
 }
 
 // --- fine and coarse preconditioner -----------------------------------------
@@ -211,17 +223,23 @@ void coarse_solve_levels(sem_mesh m, hipStream_t s) {
   const int nl = (int)T.levels.size();
   for (int k = 0; k < nl; ++k) {
     const Level& L = T.levels[k];
-    const int grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, (L.size + 3) / 4));
-    hipLaunchKernelGGL(coarse_fwd_kernel, dim3(grid), dim3(256), L.size * sizeof(double), s, m->Rlev.p, m->Wlev.p,
-                       m->ac_off.p, m->ac_col.p, m->ac_val.p, m->sinv.p + L.sinv, L.off, L.size);
+    hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(L.size)), dim3(kGS), 0, s, m->Ylev.p,
+                       m->Rlev.p, m->Wlev.p, m->ac_off.p, m->ac_col.p, m->ac_val.p, L.off, L.size, 1);
+    hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)blocks_for(L.size, 4)), dim3(256), 0, s, m->Wlev.p,
+                       m->Wlev.p, m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 0);
     SEM_HIP(hipGetLastError());
   }
   for (int k = nl - 1; k >= 0; --k) {
     const Level& L = T.levels[k];
-    const int grid = (int)std::min<int64_t>(256, std::max<int64_t>(1, (L.size + 3) / 4));
-    hipLaunchKernelGGL(coarse_bwd_kernel, dim3(grid), dim3(256), L.size * sizeof(double), s, m->Xlev.p, m->Wlev.p,
-                       m->ac_off.p, m->ac_col.p, m->ac_val.p, m->sinv.p + L.sinv, L.off, L.size,
-                       (int)(k + 1 < nl));
+    if (k == nl - 1) {
+      hipLaunchKernelGGL((copy_kernel<double, double>), dim3(grid_stride_blocks(L.size)), dim3(kGS), 0, s,
+                         m->Xlev.p + L.off, (const double*)m->Wlev.p + L.off, L.size);
+    } else {
+      hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(L.size)), dim3(kGS), 0, s, m->Ylev.p,
+                         m->Rlev.p, m->Xlev.p, m->ac_off.p, m->ac_col.p, m->ac_val.p, L.off, L.size, 0);
+      hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)blocks_for(L.size, 4)), dim3(256), 0, s, m->Xlev.p,
+                         m->Wlev.p, m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 1);
+    }
     SEM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,
@@ -262,12 +280,13 @@ void factor_coarse(sem_mesh m) {
   m->Rlev.alloc(nc);
   m->Wlev.alloc(nc);
   m->Xlev.alloc(nc);
+  m->Ylev.alloc(nc);
   if (T.nc == 0) {
     m->sinv.release();
     return;
   }
-  if (max_level(T) > 8192)
-    throw Error{SEM_EUNSUPPORTED, "coarse level of " + std::to_string(max_level(T)) + " vertices exceeds 8192"};
+  if (max_level(T) > 16384)
+    throw Error{SEM_EUNSUPPORTED, "coarse level of " + std::to_string(max_level(T)) + " vertices exceeds 16384"};
   int64_t pool = 0;
   for (auto& L : T.levels) pool += L.size * L.size;
   m->sinv.alloc(pool);
@@ -745,6 +764,52 @@ int sem_apply_A(sem_mesh m, const void* u, void* y, int dtype, void* stream) {
       apply_A<float>(m, (const float*)u, (float*)y, s);
     } else
       throw Error{SEM_EINVAL, "dtype"};
+    return SEM_OK;
+  });
+}
+
+int sem_time_apply_A(sem_mesh m, const void* u, void* y, int dtype, int reps, void* stream, double* ms_element,
+                     double* ms_gather) {
+  int st = need_device(m);
+  if (st) return st;
+  if (!u || !y || u == y || reps < 1) return SEM_EINVAL;
+  if (dtype == SEM_F32 && !m->fp32) return SEM_EUNSUPPORTED;
+  if (dtype != SEM_F64 && dtype != SEM_F32) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<hipEvent_t> ev(3 * (size_t)reps);
+    for (auto& e : ev) SEM_HIP(hipEventCreate(&e));
+    struct Cleanup {
+      std::vector<hipEvent_t>& v;
+      ~Cleanup() {
+        for (auto e : v) (void)hipEventDestroy(e);
+      }
+    } cleanup{ev};
+    for (int r = 0; r < reps; ++r) {
+      SEM_HIP(hipEventRecord(ev[3 * r], s));
+      if (dtype == SEM_F64)
+        apply_A_elements<double>(m, (const double*)u, (double*)y, s);
+      else
+        apply_A_elements<float>(m, (const float*)u, (float*)y, s);
+      SEM_HIP(hipEventRecord(ev[3 * r + 1], s));
+      if (dtype == SEM_F64)
+        launch_gs<double>(m, (double*)y, s);
+      else
+        launch_gs<float>(m, (float*)y, s);
+      SEM_HIP(hipEventRecord(ev[3 * r + 2], s));
+    }
+    SEM_HIP(hipStreamSynchronize(s));
+    double te = 0.0, tg = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      float a = 0.f, b = 0.f;
+      SEM_HIP(hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]));
+      SEM_HIP(hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]));
+      te += a;
+      tg += b;
+    }
+    if (ms_element) *ms_element = te / reps;
+    if (ms_gather) *ms_gather = tg / reps;
     return SEM_OK;
   });
 }

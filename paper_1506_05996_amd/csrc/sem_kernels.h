@@ -13,7 +13,7 @@ namespace sem {
 // elements per workgroup of the operator kernel: about 128 lanes per group
 template <int N>
 constexpr int ax_epb() {
-  return (128 / ((N + 1) * (N + 1))) > 0 ? (128 / ((N + 1) * (N + 1))) : 1;
+  return (64 / ((N + 1) * (N + 1))) > 0 ? (64 / ((N + 1) * (N + 1))) : 1;
 }
 
 __device__ __forceinline__ void unpack_coef(int32_t code, int& ai, int& aj, int& ak) {
@@ -32,14 +32,36 @@ __device__ __forceinline__ int node_class(int x, int N) { return x == 0 ? 0 : (x
 // load); interior results go straight to y, shared-node results to the work
 // array w that the gather kernel sums.
 // ---------------------------------------------------------------------------
+// value a[k] of a register array for a wave-uniform runtime index k
+template <typename T, int M>
+__device__ __forceinline__ T pick(const T (&a)[M], int k) {
+  T r = a[0];
+#pragma unroll
+  for (int m = 1; m < M; ++m) r = (m == k) ? a[m] : r;
+  return r;
+}
+
+// global id and work slot of lane (i, j)'s node in plane k, from the records
+struct NodeAddr {
+  int g, w, flags;
+};
+
+__device__ __forceinline__ NodeAddr node_addr(const int32_t* __restrict__ rec, int64_t e, int cx, int cy, int k,
+                                              int i, int j, int N) {
+  const int32_t* r = rec + ((e * kClasses + cx + 3 * cy + 9 * node_class(k, N)) * kRecInts);
+  int ai, aj, ak;
+  unpack_coef(r[1], ai, aj, ak);
+  const int off = ai * i + aj * j + ak * k;
+  return NodeAddr{r[0] + off, r[2] + off, r[3]};
+}
+
 template <int N, typename T, int EPB>
-__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
+__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1)) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
-          const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
-          int64_t E) {
+          const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir, int64_t E) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   __shared__ T sD[P];
-  __shared__ T su[EPB][P];
+  __shared__ T sU[EPB][NN];  // the element's gathered u, all planes
   __shared__ T sA[EPB][P];
   __shared__ T sB[EPB][P];
   const int tid = threadIdx.x;
@@ -47,68 +69,71 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   const int i = ij % n1, j = ij / n1;
   const int64_t e = (int64_t)blockIdx.x * EPB + le;
   const bool valid = e < E;
-  for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
-
+  const int64_t ev = valid ? e : 0;
   const int cx = node_class(i, N), cy = node_class(j, N);
-  int gb[3], wb[3], fl[3], ai[3], aj[3], ak[3];
+  for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
+  // rows i, j of D for this lane; D^T entries come from LDS and the
+  // k-direction entries, wave-uniform, from scalar loads in the plane loop
+  T Di[n1], Dj[n1];
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (valid) {
-      const int32_t* r = rec + ((e * kClasses + cx + 3 * cy + 9 * c) * kRecInts);
-      gb[c] = r[0];
-      unpack_coef(r[1], ai[c], aj[c], ak[c]);
-      wb[c] = r[2];
-      fl[c] = r[3];
-    } else {
-      gb[c] = wb[c] = fl[c] = ai[c] = aj[c] = ak[c] = 0;
-    }
+  for (int m = 0; m < n1; ++m) {
+    Di[m] = Dg[i * n1 + m];
+    Dj[m] = Dg[j * n1 + m];
   }
   T ru[n1], rw[n1];
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
-    const int c = node_class(k, N);
-    ru[k] = valid ? u[gb[c] + ai[c] * i + aj[c] * j + ak[c] * k] : T(0);
+    const NodeAddr a = node_addr(rec, ev, cx, cy, k, i, j, N);
+    ru[k] = valid ? u[a.g] : T(0);
+    sU[le][k * P + ij] = ru[k];
     rw[k] = T(0);
   }
-  const T* Ge = G + (valid ? e : 0) * 6 * NN + ij;
+  const T* Ge = G + ev * 6 * NN + ij;
+  T g0 = Ge[0 * NN], g1 = Ge[1 * NN], g2 = Ge[2 * NN], g3 = Ge[3 * NN], g4 = Ge[4 * NN], g5 = Ge[5 * NN];
   __syncthreads();
-#pragma unroll
+#pragma unroll 1
   for (int k = 0; k < n1; ++k) {
-    su[le][ij] = ru[k];
-    __syncthreads();
+    // prefetch the next plane's factors (the last iteration re-reads plane 0)
+    const T* Gn = Ge + (k + 1 < n1 ? k + 1 : 0) * P;
+    const T h0 = Gn[0 * NN], h1 = Gn[1 * NN], h2 = Gn[2 * NN], h3 = Gn[3 * NN], h4 = Gn[4 * NN], h5 = Gn[5 * NN];
+    const T* Dk = Dg + k * n1;
+    const T* su = &sU[le][k * P];
     T ur = 0, us = 0, ut = 0;
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-      ur += sD[i * n1 + m] * su[le][j * n1 + m];
-      us += sD[j * n1 + m] * su[le][m * n1 + i];
-      ut += sD[k * n1 + m] * ru[m];
+      ur += Di[m] * su[j * n1 + m];
+      us += Dj[m] * su[m * n1 + i];
+      ut += Dk[m] * ru[m];
     }
-    const T g0 = Ge[0 * NN + k * P], g1 = Ge[1 * NN + k * P], g2 = Ge[2 * NN + k * P];
-    const T g3 = Ge[3 * NN + k * P], g4 = Ge[4 * NN + k * P], g5 = Ge[5 * NN + k * P];
     const T A = g0 * ur + g1 * us + g2 * ut;
     const T B = g1 * ur + g3 * us + g4 * ut;
     const T C = g2 * ur + g4 * us + g5 * ut;
     sA[le][ij] = A;
     sB[le][ij] = B;
 #pragma unroll
-    for (int m = 0; m < n1; ++m) rw[m] += sD[k * n1 + m] * C;
+    for (int m = 0; m < n1; ++m) rw[m] += Dk[m] * C;
     __syncthreads();
     T acc = 0;
 #pragma unroll
     for (int m = 0; m < n1; ++m) acc += sD[m * n1 + i] * sA[le][j * n1 + m] + sD[m * n1 + j] * sB[le][m * n1 + i];
-    rw[k] += acc;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) rw[m] = (m == k) ? rw[m] + acc : rw[m];
+    __syncthreads();
+    g0 = h0;
+    g1 = h1;
+    g2 = h2;
+    g3 = h3;
+    g4 = h4;
+    g5 = h5;
   }
   if (!valid) return;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
-    const int c = node_class(k, N);
-    const int off = ai[c] * i + aj[c] * j + ak[c] * k;
-    if (fl[c] & kFlagInterior) {
-      const int g = gb[c] + off;
-      y[g] = dir[g] ? T(0) : rw[k];
-    } else {
-      w[wb[c] + off] = rw[k];
-    }
+    const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
+    if (a.flags & kFlagInterior)
+      y[a.g] = dir[a.g] ? T(0) : rw[k];
+    else
+      w[a.w] = rw[k];
   }
 }
 
@@ -150,17 +175,14 @@ constexpr int fdm_threads() {
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(fdm_threads<N>())
+__global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restrict__ ip,
-           const T* __restrict__ Sg, const T* __restrict__ lamg, const T* __restrict__ hg, int64_t E) {
+           const T* __restrict__ S, const T* __restrict__ lam, const T* __restrict__ hg, int64_t E) {
+  // S and lambda are read with wave-uniform indices (scalar loads)
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
-  __shared__ T S[MM];
-  __shared__ T lam[m];
   const int tid = threadIdx.x;
   const int64_t e = blockIdx.x;
-  for (int x = tid; x < MM; x += NT) S[x] = Sg[x];
-  if (tid < m) lam[tid] = lamg[tid];
   const int32_t* ipe = ip + e * MMM;
   for (int x = tid; x < MMM; x += NT) {
     const int32_t g = ipe[x];
@@ -340,59 +362,41 @@ restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, co
   R[c] = s;
 }
 
-// Block LDL^T solve of the level-ordered coarse matrix.  Forward sweep for
-// level k: yhat = R_k - A_{k,k-1} W_{k-1} (recomputed by every workgroup in
-// LDS), then W_k = Sinv_k yhat, one wave per row.
+// Block LDL^T solve of the level-ordered coarse matrix (levels couple only to
+// their neighbours).  Each level step is two launches: the sparse coupling,
+// one lane per row, then a dense product with the level's inverse Schur
+// complement, one wave per row.
+//   forward  level k: Y_k = R_k - A_{k,k-1} W_{k-1};   W_k = Sinv_k Y_k
+//   backward level k: Y_k = A_{k,k+1} X_{k+1};        X_k = W_k - Sinv_k Y_k
 __global__ void __launch_bounds__(256)
-coarse_fwd_kernel(const double* __restrict__ R, double* __restrict__ W, const int32_t* __restrict__ off,
-                  const int32_t* __restrict__ col, const double* __restrict__ val, const double* __restrict__ Sinv,
-                  int64_t loff, int64_t lsize) {
-  extern __shared__ double yh[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int64_t r = tid; r < lsize; r += nt) {
-    double s = R[loff + r];
-    for (int32_t q = off[loff + r]; q < off[loff + r + 1]; ++q)
-      if (col[q] < loff) s -= val[q] * W[col[q]];
-    yh[r] = s;
+coarse_couple_kernel(double* __restrict__ Y, const double* __restrict__ R, const double* __restrict__ V,
+                     const int32_t* __restrict__ off, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t loff, int64_t lsize, int forward) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= lsize) return;
+  const int64_t row = loff + r, nxt = loff + lsize;
+  double s = forward ? R[row] : 0.0;
+  for (int32_t q = off[row]; q < off[row + 1]; ++q) {
+    const int32_t c = col[q];
+    if (forward && c < loff) s -= val[q] * V[c];
+    if (!forward && c >= nxt) s += val[q] * V[c];
   }
-  __syncthreads();
-  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  for (int64_t row = (int64_t)blockIdx.x * nw + wave; row < lsize; row += (int64_t)gridDim.x * nw) {
-    const double* Sr = Sinv + row * lsize;
-    double s = 0.0;
-    for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * yh[c];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) W[loff + row] = s;
-  }
+  Y[row] = s;
 }
 
-// Backward sweep for level k: X_k = W_k - Sinv_k (A_{k,k+1} X_{k+1}).
+// Out_k = (sub ? W_k - S Y_k : S Y_k), S dense symmetric lsize x lsize
 __global__ void __launch_bounds__(256)
-coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ W, const int32_t* __restrict__ off,
-                  const int32_t* __restrict__ col, const double* __restrict__ val, const double* __restrict__ Sinv,
-                  int64_t loff, int64_t lsize, int has_next) {
-  extern __shared__ double tt[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t nxt = loff + lsize;
-  const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-  if (!has_next) {
-    for (int64_t r = (int64_t)blockIdx.x * nt + tid; r < lsize; r += (int64_t)gridDim.x * nt) X[loff + r] = W[loff + r];
-    return;
-  }
-  for (int64_t r = tid; r < lsize; r += nt) {
-    double s = 0.0;
-    for (int32_t q = off[loff + r]; q < off[loff + r + 1]; ++q)
-      if (col[q] >= nxt) s += val[q] * X[col[q]];
-    tt[r] = s;
-  }
-  __syncthreads();
-  for (int64_t row = (int64_t)blockIdx.x * nw + wave; row < lsize; row += (int64_t)gridDim.x * nw) {
-    const double* Sr = Sinv + row * lsize;
-    double s = 0.0;
-    for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * tt[c];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) X[loff + row] = W[loff + row] - s;
-  }
+coarse_gemv_kernel(double* __restrict__ Out, const double* __restrict__ W, const double* __restrict__ Y,
+                   const double* __restrict__ S, int64_t loff, int64_t lsize, int sub) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= lsize) return;
+  const double* Sr = S + row * lsize;
+  const double* y = Y + loff;
+  double s = 0.0;
+  for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * y[c];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) Out[loff + row] = sub ? W[loff + row] - s : s;
 }
 
 // vertex-indexed coarse solution (0 on Dirichlet vertices)

@@ -35,7 +35,7 @@ EXPORTS = [
     "sem_mesh_sizes", "sem_mesh_numbering", "sem_mesh_gs_csr", "sem_mesh_patch_table",
     "sem_mesh_node_coords", "sem_mesh_lumped_mass", "sem_mesh_boundary_mask", "sem_mesh_geometry",
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
-    "sem_last_error",
+    "sem_time_apply_A", "sem_last_error",
 ]
 
 
@@ -74,11 +74,9 @@ _lib.sem_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, _p]
 _lib.sem_precond.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p]
 _lib.sem_coarse_solve.argtypes = [_p, _p, _p, _p]
 _lib.sem_pcg_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
+_lib.sem_time_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
 _lib.sem_last_error.restype = ctypes.c_char_p
-for name in EXPORTS:
-    fn = getattr(_lib, name)
-    if fn.restype is None and name not in ("sem_default_setup_opts", "sem_default_solve_opts"):
-        pass
 
 
 class SemError(RuntimeError):
@@ -141,9 +139,9 @@ class Mesh:
         self.host_only = host_only
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.sem_mesh_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -224,6 +222,15 @@ class Mesh:
             raise TypeError("u and y must share a dtype")
         _check(_lib.sem_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), _stream(stream)))
         return y
+
+    def time_apply_A(self, u, y, reps, stream=None):
+        """Mean (element kernel, gather kernel) durations in ms over `reps` applies."""
+        self._check_vec(u)
+        self._check_vec(y)
+        te, tg = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.sem_time_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), int(reps), _stream(stream),
+                                     ctypes.byref(te), ctypes.byref(tg)))
+        return te.value, tg.value
 
     def precond(self, r, z=None, pc=PC_TWOSCALE, stream=None):
         import torch
