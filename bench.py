@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pcg-reps", type=int, default=1)
+    ap.add_argument("--counters", action="store_true",
+                    help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
@@ -119,6 +121,17 @@ def main():
 
     u = torch.tensor(np.random.default_rng(1506).uniform(-1, 1, ng), device=dev)
     y = torch.empty_like(u)
+    if args.counters:
+        # rocprofv3 --pmc runs: the operator, then a plain device copy of
+        # n_global doubles (known bytes) that calibrates the counters
+        for _ in range(3):
+            M.apply_A(u, y)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            y.copy_(u)
+        torch.cuda.synchronize()
+        log(f"[bench] counters run done: copy bytes per launch {8 * ng} read + {8 * ng} written")
+        return
     for _ in range(args.warmup):
         M.apply_A(u, y)
     torch.cuda.synchronize()

@@ -70,7 +70,7 @@ struct sem_mesh_s {
   bool fp32 = true;
   int device = 0;
   // numbering / gather
-  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx;
+  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx, order;
   DBuf<uint8_t> dir, fcount;
   // operator
   DBuf<double> G64, D64, w64;
@@ -143,9 +143,9 @@ template <int N, typename T>
 void launch_ax(sem_mesh m, const T* u, T* y, hipStream_t s) {
   constexpr int EPB = ax_epb<N>();
   const HostTables& T_ = m->T;
-  const int64_t grid = (T_.E + EPB - 1) / EPB;
+  const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
   hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
-                     Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, T_.E);
+                     Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
   SEM_HIP(hipGetLastError());
 }
 
@@ -183,15 +183,15 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
 // --- fine and coarse preconditioner -----------------------------------------
 template <int N, typename T>
 void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
-  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)m->T.E), dim3(fdm_threads<N>()), 0, s, r, ZPp<T>(m),
-                     m->ip.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->T.E);
+  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r,
+                     ZPp<T>(m), m->ip.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E);
   SEM_HIP(hipGetLastError());
 }
 
 template <int N, typename T>
 void launch_restrict(sem_mesh m, const T* r, hipStream_t s) {
-  hipLaunchKernelGGL((restrict_kernel<N, T>), dim3((unsigned)m->T.E), dim3((N + 1) * (N + 1)), 0, s, r, m->Re.p,
-                     m->rec.p, m->phi.p, m->T.E);
+  hipLaunchKernelGGL((restrict_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3((N + 1) * (N + 1)), 0, s, r,
+                     m->Re.p, m->rec.p, m->phi.p, m->order.p, m->T.E);
   SEM_HIP(hipGetLastError());
 }
 
@@ -352,6 +352,7 @@ void upload_all(sem_mesh m) {
   HostTables& T = m->T;
   SEM_HIP(hipSetDevice(m->device));
   m->rec.upload(T.rec.data(), T.rec.size());
+  m->order.upload(T.order.data(), T.order.size());
   m->vinc_off.upload(T.vinc_off.data(), T.vinc_off.size());
   m->einc_off.upload(T.einc_off.data(), T.einc_off.size());
   m->owner.upload(T.owner.data(), T.owner.size());
@@ -740,10 +741,12 @@ int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask) {
     for (int64_t g = 0; g < T.n_global; ++g) T.dir[g] = mask[g] ? 1 : 0;
     // the coarse free set follows the vertex nodes: new levels, new factor
     build_coarse_levels(T);
+    update_interior_mask_flags(T);
     if (!m->host_only) {
       SEM_HIP(hipSetDevice(m->device));
       SEM_HIP(hipDeviceSynchronize());
       m->dir.upload(T.dir.data(), T.dir.size());
+      m->rec.upload(T.rec.data(), T.rec.size());
       factor_coarse(m);
     }
     return SEM_OK;

@@ -34,6 +34,7 @@ constexpr int kClasses = 27;
 constexpr int kInteriorClass = 13;
 constexpr int kFlagOwned = 1;     // this element holds the first local copy of the node
 constexpr int kFlagInterior = 2;  // interior node: written straight to the global vector
+constexpr int kFlagMaskedInterior = 4;  // (interior record) some interior node of the element is Dirichlet
 
 inline int32_t pack_coef(int ai, int aj, int ak) {
   return (ai & 0x3FF) | ((aj & 0x3FF) << 10) | ((ak & 0x3FF) << 20);
@@ -75,6 +76,7 @@ struct HostTables {
   std::vector<double> mN;    // [n_global]
   std::vector<double> xN;    // [n_global][3]
   std::vector<double> h;     // [E][3]
+  std::vector<int32_t> order;  // element traversal order: Morton order of the centroids
 
   // coarse space (order-1 operator on the free vertices, level-ordered)
   std::vector<int32_t> cidx;             // [V] coarse index or -1 (Dirichlet vertex)
@@ -93,6 +95,7 @@ void build_patches(HostTables& T, const int64_t* hex);
 void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex);
 void build_coarse_levels(HostTables& T);
 void export_l2g(const HostTables& T, int32_t* l2g);
+void update_interior_mask_flags(HostTables& T);
 int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k);
 
 }  // namespace sem

@@ -55,10 +55,21 @@ __device__ __forceinline__ NodeAddr node_addr(const int32_t* __restrict__ rec, i
   return NodeAddr{r[0] + off, r[2] + off, r[3]};
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b on XCD b % 8):
+// give each XCD one contiguous run of the traversal order so that elements
+// that share faces, edges and vertices meet in the same L2.
+__device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nlogical) {
+  const int64_t per = (nlogical + 7) / 8;
+  return (b & 7) * per + (b >> 3);
+}
+
+inline int64_t xcd_grid(int64_t nlogical) { return ((nlogical + 7) / 8) * 8; }
+
 template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1)) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
-          const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir, int64_t E) {
+          const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
+          const int32_t* __restrict__ order, int64_t E) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   __shared__ T sD[P];
   __shared__ T sU[EPB][NN];  // the element's gathered u, all planes
@@ -67,43 +78,34 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   const int tid = threadIdx.x;
   const int le = tid / P, ij = tid - le * P;
   const int i = ij % n1, j = ij / n1;
-  const int64_t e = (int64_t)blockIdx.x * EPB + le;
-  const bool valid = e < E;
-  const int64_t ev = valid ? e : 0;
+  const int64_t pos = xcd_position(blockIdx.x, (E + EPB - 1) / EPB) * EPB + le;
+  const bool valid = pos < E;
+  const int64_t e = valid ? order[pos] : 0;
   const int cx = node_class(i, N), cy = node_class(j, N);
   for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
-  // rows i, j of D for this lane; D^T entries come from LDS and the
-  // k-direction entries, wave-uniform, from scalar loads in the plane loop
-  T Di[n1], Dj[n1];
-#pragma unroll
-  for (int m = 0; m < n1; ++m) {
-    Di[m] = Dg[i * n1 + m];
-    Dj[m] = Dg[j * n1 + m];
-  }
-  T ru[n1], rw[n1];
+  T rw[n1];
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
-    const NodeAddr a = node_addr(rec, ev, cx, cy, k, i, j, N);
-    ru[k] = valid ? u[a.g] : T(0);
-    sU[le][k * P + ij] = ru[k];
+    const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
+    sU[le][k * P + ij] = valid ? u[a.g] : T(0);
     rw[k] = T(0);
   }
-  const T* Ge = G + ev * 6 * NN + ij;
+  // factors of plane k in registers, plane k+1 prefetched during plane k
+  const T* Ge = G + e * 6 * NN + ij;
   T g0 = Ge[0 * NN], g1 = Ge[1 * NN], g2 = Ge[2 * NN], g3 = Ge[3 * NN], g4 = Ge[4 * NN], g5 = Ge[5 * NN];
   __syncthreads();
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
-    // prefetch the next plane's factors (the last iteration re-reads plane 0)
     const T* Gn = Ge + (k + 1 < n1 ? k + 1 : 0) * P;
     const T h0 = Gn[0 * NN], h1 = Gn[1 * NN], h2 = Gn[2 * NN], h3 = Gn[3 * NN], h4 = Gn[4 * NN], h5 = Gn[5 * NN];
-    const T* Dk = Dg + k * n1;
+    const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
     const T* su = &sU[le][k * P];
     T ur = 0, us = 0, ut = 0;
 #pragma unroll
     for (int m = 0; m < n1; ++m) {
-      ur += Di[m] * su[j * n1 + m];
-      us += Dj[m] * su[m * n1 + i];
-      ut += Dk[m] * ru[m];
+      ur += sD[i * n1 + m] * su[j * n1 + m];
+      us += sD[j * n1 + m] * su[m * n1 + i];
+      ut += Dk[m] * sU[le][m * P + ij];
     }
     const T A = g0 * ur + g1 * us + g2 * ut;
     const T B = g1 * ur + g3 * us + g4 * ut;
@@ -127,11 +129,12 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     g5 = h5;
   }
   if (!valid) return;
+  const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
     const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
     if (a.flags & kFlagInterior)
-      y[a.g] = dir[a.g] ? T(0) : rw[k];
+      y[a.g] = (masked_interior && dir[a.g]) ? T(0) : rw[k];
     else
       w[a.w] = rw[k];
   }
@@ -177,12 +180,15 @@ constexpr int fdm_threads() {
 template <int N, typename T>
 __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restrict__ ip,
-           const T* __restrict__ S, const T* __restrict__ lam, const T* __restrict__ hg, int64_t E) {
+           const T* __restrict__ S, const T* __restrict__ lam, const T* __restrict__ hg,
+           const int32_t* __restrict__ order, int64_t E) {
   // S and lambda are read with wave-uniform indices (scalar loads)
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
   const int tid = threadIdx.x;
-  const int64_t e = blockIdx.x;
+  const int64_t pos = xcd_position(blockIdx.x, E);
+  if (pos >= E) return;
+  const int64_t e = order[pos];
   const int32_t* ipe = ip + e * MMM;
   for (int x = tid; x < MMM; x += NT) {
     const int32_t g = ipe[x];
@@ -316,12 +322,14 @@ precond_gather_kernel(T* __restrict__ z, const T* __restrict__ zP, const int32_t
 template <int N, typename T>
 __global__ void __launch_bounds__((N + 1) * (N + 1))
 restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t* __restrict__ rec,
-                const double* __restrict__ phi, int64_t E) {
+                const double* __restrict__ phi, const int32_t* __restrict__ order, int64_t E) {
   constexpr int n1 = N + 1, P = n1 * n1;
   __shared__ double red[8][P];
   const int tid = threadIdx.x;
   const int i = tid % n1, j = tid / n1;
-  const int64_t e = blockIdx.x;
+  const int64_t pos = xcd_position(blockIdx.x, E);
+  if (pos >= E) return;
+  const int64_t e = order[pos];
   const int cx = node_class(i, N), cy = node_class(j, N);
   double acc[8];
 #pragma unroll

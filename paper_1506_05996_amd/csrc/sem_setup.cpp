@@ -479,6 +479,8 @@ void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n
         }
     }
 
+  update_interior_mask_flags(T);
+
   // first local copy of every global node
   T.owner.assign(T.n_global, -1);
   for (int64_t e = 0; e < E; ++e)
@@ -488,6 +490,24 @@ void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n
           int64_t g = gid_of(T, e, i, j, k);
           if (T.owner[g] < 0) T.owner[g] = (int32_t)(e * n1 * n1 * n1 + i + n1 * (j + n1 * k));
         }
+}
+
+// flag elements whose interior holds a Dirichlet node (never the case for the
+// topological boundary): only those need the mask on their direct writes
+void update_interior_mask_flags(HostTables& T) {
+  const int N = T.N;
+  for (int64_t e = 0; e < T.E; ++e) {
+    int32_t* r = &T.rec[((size_t)e * kClasses + kInteriorClass) * kRecInts];
+    bool any = false;
+    for (int k = 1; k < N && !any; ++k)
+      for (int j = 1; j < N && !any; ++j)
+        for (int i = 1; i < N; ++i)
+          if (T.dir[gid_of(T, e, i, j, k)]) {
+            any = true;
+            break;
+          }
+    r[3] = any ? (r[3] | kFlagMaskedInterior) : (r[3] & ~kFlagMaskedInterior);
+  }
 }
 
 void export_l2g(const HostTables& T, int32_t* l2g) {
@@ -594,6 +614,33 @@ void build_geometry(HostTables& T, const double* vtx, const int64_t* hex) {
   });
   for (int64_t e = 0; e < E; ++e)
     if (badel[e]) throw Error{SEM_EMESH, "inverted or degenerate hexahedron (|J| <= 0 at a GLL node)"};
+  // traversal order: Morton (Z-order) key of the element centroids, 21 bits per axis
+  {
+    std::vector<double> cen((size_t)E * 3, 0.0);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t e = 0; e < E; ++e)
+      for (int r = 0; r < 3; ++r) {
+        double c = 0.0;
+        for (int p = 0; p < 8; ++p) c += vtx[hex[e * 8 + p] * 3 + r];
+        c *= 0.125;
+        cen[e * 3 + r] = c;
+        lo[r] = std::min(lo[r], c);
+        hi[r] = std::max(hi[r], c);
+      }
+    std::vector<std::pair<uint64_t, int32_t>> key(E);
+    for (int64_t e = 0; e < E; ++e) {
+      uint64_t m = 0;
+      for (int r = 0; r < 3; ++r) {
+        const double span = hi[r] > lo[r] ? hi[r] - lo[r] : 1.0;
+        const uint32_t q = (uint32_t)std::min(2097151.0, (cen[e * 3 + r] - lo[r]) / span * 2097151.0);
+        for (int bit = 0; bit < 21; ++bit) m |= (uint64_t)((q >> bit) & 1u) << (3 * bit + r);
+      }
+      key[e] = {m, (int32_t)e};
+    }
+    std::sort(key.begin(), key.end());
+    T.order.resize(E);
+    for (int64_t e = 0; e < E; ++e) T.order[e] = key[e].second;
+  }
   // lumped mass: copies summed in ascending local index; coordinates of the first copy
   T.mN.assign(T.n_global, 0.0);
   T.xN.assign(T.n_global * 3, 0.0);
