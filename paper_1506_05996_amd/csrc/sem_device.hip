@@ -81,7 +81,10 @@ struct sem_mesh_s {
   DBuf<float> S32, lam32, h32, zP32;
   // coarse
   DBuf<double> phi, Re, Rlev, Wlev, Xlev, Ylev, Zv, sinv, ac_val;
-  DBuf<int32_t> ac_off, ac_col;
+  DBuf<int32_t> ac_off, ac_col, lo_off, lo_col, up_off, up_col;
+  DBuf<double> lo_val, up_val;
+  hipGraphExec_t coarse_graph = nullptr;  // the level sweeps, captured once per factorisation
+  hipStream_t capture_stream = nullptr;
   // PCG work
   DBuf<double> v64[5];
   DBuf<float> v32[5];
@@ -218,15 +221,15 @@ size_t max_level(const HostTables& T) {
 }
 
 // Rlev (level order) -> Zv (vertex order): block LDL^T sweeps
-void coarse_solve_levels(sem_mesh m, hipStream_t s) {
+void coarse_sweeps(sem_mesh m, hipStream_t s) {
   const HostTables& T = m->T;
   const int nl = (int)T.levels.size();
   for (int k = 0; k < nl; ++k) {
     const Level& L = T.levels[k];
-    hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(L.size)), dim3(kGS), 0, s, m->Ylev.p,
-                       m->Rlev.p, m->Wlev.p, m->ac_off.p, m->ac_col.p, m->ac_val.p, L.off, L.size, 1);
-    hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)blocks_for(L.size, 4)), dim3(256), 0, s, m->Wlev.p,
-                       m->Wlev.p, m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 0);
+    hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
+                       m->Rlev.p, m->Wlev.p, m->lo_off.p, m->lo_col.p, m->lo_val.p, L.off, L.size, 1);
+    hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Wlev.p, m->Wlev.p, m->Ylev.p,
+                       m->sinv.p + L.sinv, L.off, L.size, 0);
     SEM_HIP(hipGetLastError());
   }
   for (int k = nl - 1; k >= 0; --k) {
@@ -235,16 +238,45 @@ void coarse_solve_levels(sem_mesh m, hipStream_t s) {
       hipLaunchKernelGGL((copy_kernel<double, double>), dim3(grid_stride_blocks(L.size)), dim3(kGS), 0, s,
                          m->Xlev.p + L.off, (const double*)m->Wlev.p + L.off, L.size);
     } else {
-      hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(L.size)), dim3(kGS), 0, s, m->Ylev.p,
-                         m->Rlev.p, m->Xlev.p, m->ac_off.p, m->ac_col.p, m->ac_val.p, L.off, L.size, 0);
-      hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)blocks_for(L.size, 4)), dim3(256), 0, s, m->Xlev.p,
-                         m->Wlev.p, m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 1);
+      hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
+                         m->Rlev.p, m->Xlev.p, m->up_off.p, m->up_col.p, m->up_val.p, L.off, L.size, 0);
+      hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Xlev.p, m->Wlev.p,
+                         m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 1);
     }
     SEM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,
                      m->cidx.p, T.V);
   SEM_HIP(hipGetLastError());
+}
+
+void release_coarse_graph(sem_mesh m) {
+  if (m->coarse_graph) (void)hipGraphExecDestroy(m->coarse_graph);
+  m->coarse_graph = nullptr;
+}
+
+// capture the sweeps once (on a private stream) and replay them on the caller's stream
+void coarse_solve_levels(sem_mesh m, hipStream_t s) {
+  if (!m->coarse_graph) {
+    if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    SEM_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      coarse_sweeps(m, m->capture_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(m->capture_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SEM_HIP(hipStreamEndCapture(m->capture_stream, &g));
+    hipError_t err = hipGraphInstantiate(&m->coarse_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) {
+      m->coarse_graph = nullptr;
+      throw Error{SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
+    }
+  }
+  SEM_HIP(hipGraphLaunch(m->coarse_graph, s));
 }
 
 template <typename T>
@@ -272,9 +304,16 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
 // --- coarse factorisation (set-up): Sinv_k = S_k^{-1}, S_k the Schur complements
 void factor_coarse(sem_mesh m) {
   HostTables& T = m->T;
+  release_coarse_graph(m);
   m->ac_off.upload(T.ac_off.data(), T.ac_off.size());
   m->ac_col.upload(T.ac_col.data(), T.ac_col.size());
   m->ac_val.upload(T.ac_val.data(), T.ac_val.size());
+  m->lo_off.upload(T.lo_off.data(), T.lo_off.size());
+  m->lo_col.upload(T.lo_col.data(), T.lo_col.size());
+  m->lo_val.upload(T.lo_val.data(), T.lo_val.size());
+  m->up_off.upload(T.up_off.data(), T.up_off.size());
+  m->up_col.upload(T.up_col.data(), T.up_col.size());
+  m->up_val.upload(T.up_val.data(), T.up_val.size());
   m->cidx.upload(T.cidx.data(), T.cidx.size());
   const size_t nc = std::max<int64_t>(T.nc, 1);
   m->Rlev.alloc(nc);
@@ -285,6 +324,7 @@ void factor_coarse(sem_mesh m) {
     m->sinv.release();
     return;
   }
+  // dense inverse Schur complements are kept per level: bound their size
   if (max_level(T) > 16384)
     throw Error{SEM_EUNSUPPORTED, "coarse level of " + std::to_string(max_level(T)) + " vertices exceeds 16384"};
   int64_t pool = 0;
@@ -667,7 +707,12 @@ int sem_mesh_setup(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t
 
 int sem_mesh_destroy(sem_mesh m) {
   if (!m) return SEM_OK;
-  if (!m->host_only) (void)hipSetDevice(m->device);
+  if (!m->host_only) {
+    (void)hipSetDevice(m->device);
+    (void)hipDeviceSynchronize();
+    release_coarse_graph(m);
+    if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
+  }
   delete m;
   return SEM_OK;
 }

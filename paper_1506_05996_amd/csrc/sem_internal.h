@@ -84,6 +84,8 @@ struct HostTables {
   std::vector<Level> levels;
   std::vector<int32_t> ac_off, ac_col;   // CSR of A_c in level order
   std::vector<double> ac_val;
+  std::vector<int32_t> lo_off, lo_col, up_off, up_col;  // couplings to the previous / next level
+  std::vector<double> lo_val, up_val;
   std::vector<double> corner_K;          // [E][8][8] order-1 element matrices
 };
 

@@ -371,40 +371,58 @@ restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, co
 }
 
 // Block LDL^T solve of the level-ordered coarse matrix (levels couple only to
-// their neighbours).  Each level step is two launches: the sparse coupling,
-// one lane per row, then a dense product with the level's inverse Schur
-// complement, one wave per row.
+// their neighbours).  Each level step is two launches: the sparse coupling
+// with the neighbouring level, then a dense product with the level's inverse
+// Schur complement.
 //   forward  level k: Y_k = R_k - A_{k,k-1} W_{k-1};   W_k = Sinv_k Y_k
 //   backward level k: Y_k = A_{k,k+1} X_{k+1};        X_k = W_k - Sinv_k Y_k
+// The coupling lists hold only the entries towards the neighbouring level
+// (lower for the forward sweep, upper for the backward one); 8 lanes per row.
 __global__ void __launch_bounds__(256)
 coarse_couple_kernel(double* __restrict__ Y, const double* __restrict__ R, const double* __restrict__ V,
                      const int32_t* __restrict__ off, const int32_t* __restrict__ col,
                      const double* __restrict__ val, int64_t loff, int64_t lsize, int forward) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= lsize) return;
-  const int64_t row = loff + r, nxt = loff + lsize;
-  double s = forward ? R[row] : 0.0;
-  for (int32_t q = off[row]; q < off[row + 1]; ++q) {
-    const int32_t c = col[q];
-    if (forward && c < loff) s -= val[q] * V[c];
-    if (!forward && c >= nxt) s += val[q] * V[c];
-  }
-  Y[row] = s;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t r = gid >> 3;
+  const int sub = (int)(gid & 7);
+  if (r >= lsize) return;  // whole 8-lane groups leave together
+  const int64_t row = loff + r;
+  double s = 0.0;
+  for (int32_t q = off[row] + sub; q < off[row + 1]; q += 8) s += val[q] * V[col[q]];
+  s += __shfl_xor(s, 4, 8);
+  s += __shfl_xor(s, 2, 8);
+  s += __shfl_xor(s, 1, 8);
+  if (sub == 0) Y[row] = forward ? R[row] - s : s;
 }
 
-// Out_k = (sub ? W_k - S Y_k : S Y_k), S dense symmetric lsize x lsize
+// Out_k = (sub ? W_k - S Y_k : S Y_k), S dense symmetric lsize x lsize: one
+// workgroup per row, its four waves take one quarter of the columns each with
+// eight independent partial sums per lane.
 __global__ void __launch_bounds__(256)
 coarse_gemv_kernel(double* __restrict__ Out, const double* __restrict__ W, const double* __restrict__ Y,
                    const double* __restrict__ S, int64_t loff, int64_t lsize, int sub) {
-  const int lane = threadIdx.x & 63;
-  const int64_t row = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  __shared__ double part[4];
+  const int64_t row = blockIdx.x;
   if (row >= lsize) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t q4 = (lsize + 3) / 4, c0 = wave * q4, c1 = c0 + q4 < lsize ? c0 + q4 : lsize;
   const double* Sr = S + row * lsize;
   const double* y = Y + loff;
-  double s = 0.0;
-  for (int64_t c = lane; c < lsize; c += 64) s += Sr[c] * y[c];
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t c = c0 + lane;
+  for (; c + 448 < c1; c += 512) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a[q] += Sr[c + 64 * q] * y[c + 64 * q];
+  }
+  for (; c < c1; c += 64) a[0] += Sr[c] * y[c];
+  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) Out[loff + row] = sub ? W[loff + row] - s : s;
+  if (lane == 0) part[wave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double t = (part[0] + part[1]) + (part[2] + part[3]);
+    Out[loff + row] = sub ? W[loff + row] - t : t;
+  }
 }
 
 // vertex-indexed coarse solution (0 on Dirichlet vertices)

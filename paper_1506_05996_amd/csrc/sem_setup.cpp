@@ -968,6 +968,31 @@ void build_coarse_levels(HostTables& T) {
     }
     T.ac_off[r + 1] = (int32_t)T.ac_col.size();
   }
+  // coupling lists of each row towards the previous and the next level
+  std::vector<int64_t> lev_of(T.nc);
+  for (size_t l = 0; l < T.levels.size(); ++l)
+    for (int64_t r = T.levels[l].off; r < T.levels[l].off + T.levels[l].size; ++r) lev_of[r] = (int64_t)l;
+  T.lo_off.assign(T.nc + 1, 0);
+  T.up_off.assign(T.nc + 1, 0);
+  T.lo_col.clear();
+  T.up_col.clear();
+  T.lo_val.clear();
+  T.up_val.clear();
+  for (int64_t r = 0; r < T.nc; ++r) {
+    const Level& L = T.levels[lev_of[r]];
+    for (int32_t q = T.ac_off[r]; q < T.ac_off[r + 1]; ++q) {
+      const int32_t c = T.ac_col[q];
+      if (c < L.off) {
+        T.lo_col.push_back(c);
+        T.lo_val.push_back(T.ac_val[q]);
+      } else if (c >= L.off + L.size) {
+        T.up_col.push_back(c);
+        T.up_val.push_back(T.ac_val[q]);
+      }
+    }
+    T.lo_off[r + 1] = (int32_t)T.lo_col.size();
+    T.up_off[r + 1] = (int32_t)T.up_col.size();
+  }
 }
 
 }  // namespace sem
