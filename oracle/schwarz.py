@@ -230,6 +230,23 @@ def patch_table(num: Numbering, hexes, elements=None) -> np.ndarray:
     return out
 
 
+def fdm_patch_solve(S, lam, r_s, h, kappa=1.0, c=0.0):
+    """eq. (z) for patches r_s[s, c, b, a] with box sizes h[s, 3] (step 4)."""
+    t = np.einsum("xa,...cbx->...cba", S, r_s)
+    t = np.einsum("xb,...cxa->...cba", S, t)
+    t = np.einsum("xc,...xba->...cba", S, t)
+    hx, hy, hz = h[..., 0], h[..., 1], h[..., 2]
+    diag = (4.0 * kappa * (lam[None, None, None, :] / hx[:, None, None, None] ** 2
+                           + lam[None, None, :, None] / hy[:, None, None, None] ** 2
+                           + lam[None, :, None, None] / hz[:, None, None, None] ** 2)
+            + c)
+    t = t / diag
+    t = np.einsum("ax,...cbx->...cba", S, t)
+    t = np.einsum("bx,...cxa->...cba", S, t)
+    t = np.einsum("cx,...xba->...cba", S, t)
+    return t * (8.0 / (hx * hy * hz))[:, None, None, None]
+
+
 class FinePreconditioner:
     def __init__(self, num: Numbering, hexes, vtx, gll: GLL, box, kappa=1.0, c=0.0):
         self.num = num
@@ -242,20 +259,7 @@ class FinePreconditioner:
 
     def patch_solve(self, r_s: np.ndarray, h) -> np.ndarray:
         """eq. (z) for one or more patches r_s[..., c, b, a] with sizes h[..., 3]."""
-        S, lam = self.S, self.lam
-        t = np.einsum("xa,...cbx->...cba", S, r_s)
-        t = np.einsum("xb,...cxa->...cba", S, t)
-        t = np.einsum("xc,...xba->...cba", S, t)
-        hx, hy, hz = h[..., 0], h[..., 1], h[..., 2]
-        diag = (4.0 * self.kappa * (lam[None, None, None, :] / hx[:, None, None, None] ** 2
-                                    + lam[None, None, :, None] / hy[:, None, None, None] ** 2
-                                    + lam[None, :, None, None] / hz[:, None, None, None] ** 2)
-                + self.c)
-        t = t / diag
-        t = np.einsum("ax,...cbx->...cba", S, t)
-        t = np.einsum("bx,...cxa->...cba", S, t)
-        t = np.einsum("cx,...xba->...cba", S, t)
-        return t * (8.0 / (hx * hy * hz))[:, None, None, None]
+        return fdm_patch_solve(self.S, self.lam, r_s, h, self.kappa, self.c)
 
     def apply(self, r: np.ndarray) -> np.ndarray:
         Ip = self.Ip
