@@ -59,6 +59,10 @@ typedef struct {
   int host_only;     /* 1: build the host tables only (numbering, geometry, patches) and
                         allocate nothing on a device; hot-path calls return SEM_EUNSUPPORTED */
   int build_fp32;    /* 1: also keep FP32 copies for SEM_F32 calls and the refined solve (default 1) */
+  int autotune;      /* 1: time the operator kernel's tile candidates (elements per workgroup) on this
+                        mesh at set-up and keep the fastest per dtype (default 1) */
+  const char* tune_cache; /* optional text file of tuned tiles, read before and appended after tuning
+                        (NULL: no file) */
 } sem_setup_opts;
 
 typedef struct {
@@ -177,6 +181,33 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
                   sem_solve_stats* st, void* stream);
 
 /*
+ * Batched solves: many independent meshes (of any orders in 2..15) solved
+ * together.  Instances of one order share every kernel launch (their meshes
+ * are concatenated into one disjoint union), scalars of Algorithm 1 are kept
+ * per instance, and one PCG iteration of the whole batch is captured once in a
+ * hipGraph and replayed.  Each instance uses its default Dirichlet set and
+ * starts from x = 0; results match per-instance sem_pcg_solve calls.
+ */
+typedef struct sem_batch_s* sem_batch;
+
+/* n instances; vtx[i] ([n_vtx[i]][3]) and hex[i] ([n_hex[i]][8]) are host arrays
+   as for sem_mesh_setup, order[i] in 2..15.  Same errors as sem_mesh_setup. */
+int sem_batch_setup(int n, const double* const* vtx, const int64_t* n_vtx, const int64_t* const* hex,
+                    const int64_t* n_hex, const int* order, const sem_setup_opts* opts, sem_batch* out);
+
+/* n_global[i] of every instance (host out, [n]). */
+int sem_batch_sizes(sem_batch b, int64_t* n_global);
+
+/* Solve A_i x_i = b_i for all instances.  b_dev, x_dev: host arrays of n device
+   pointers (FP64, [n_global[i]] each, in each instance's own numbering).
+   st: optional array of n statistics.  Returns SEM_OK when every instance
+   converged, SEM_ENOCONV or SEM_EBREAKDOWN otherwise (statistics filled). */
+int sem_batch_solve(sem_batch b, const double* const* b_dev, double* const* x_dev, const sem_solve_opts* o,
+                    sem_solve_stats* st, void* stream);
+
+int sem_batch_destroy(sem_batch b);
+
+/*
  * sem_time_apply_A -- run `reps` applications of sem_apply_A back to back on
  * `stream` with HIP events recorded around each of its two kernels (element
  * kernel, shared-node gather), synchronise, and return the mean duration of
@@ -185,6 +216,13 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
  */
 int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int reps, void* stream,
                      double* ms_element, double* ms_gather);
+
+/* Tile of the operator kernel for dtype: elements per workgroup (1, 2, 4, 8;
+   (N+1)^2 lanes each, at most 1024 lanes), or 16 for the matrix-core kernel
+   (FP64 at N = 15 only).  Chosen by the autotuner or the default for the
+   order; sem_mesh_set_tile overrides it (SEM_EINVAL if not available). */
+int sem_mesh_tile(sem_mesh m, int dtype, int* epb);
+int sem_mesh_set_tile(sem_mesh m, int dtype, int epb);
 
 const char* sem_last_error(void);
 

@@ -1,0 +1,103 @@
+// Device-side state of a sem_mesh handle and the internal operations shared by
+// the single-mesh entry points (sem_device.hip) and the batched solver
+// (sem_batch.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <functional>
+#include <string>
+
+#include "sem_internal.h"
+
+namespace sem {
+
+#define SEM_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t err_ = (call);                                                             \
+    if (err_ != hipSuccess)                                                               \
+      throw ::sem::Error{SEM_EHIP, std::string(#call) + ": " + hipGetErrorString(err_)}; \
+  } while (0)
+
+// device buffer owned by a handle
+template <typename T>
+struct DBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  void alloc(size_t count) {
+    release();
+    if (count == 0) return;
+    hipError_t err = hipMalloc((void**)&p, count * sizeof(T));
+    if (err != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      throw Error{SEM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
+    }
+    n = count;
+  }
+  void upload(const T* h, size_t count) {
+    alloc(count);
+    if (count) SEM_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  ~DBuf() { release(); }
+};
+
+template <typename TD, typename TS>
+static std::vector<TD> convert(const std::vector<TS>& v) {
+  return std::vector<TD>(v.begin(), v.end());
+}
+
+}  // namespace sem
+
+using namespace sem;
+
+struct sem_mesh_s {
+  HostTables T;
+  bool host_only = false;
+  bool fp32 = true;
+  int device = 0;
+  // numbering / gather
+  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx, order;
+  DBuf<uint8_t> dir, fcount;
+  // operator
+  DBuf<double> G64, D64, w64;
+  DBuf<float> G32, D32, w32;
+  // fine preconditioner
+  DBuf<int32_t> ip, ip_off, ip_slot;
+  DBuf<double> S64, lam64, h64, zP64;
+  DBuf<float> S32, lam32, h32, zP32;
+  // coarse
+  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Ylev, Zv, sinv, ac_val;
+  DBuf<int32_t> ac_off, ac_col, lo_off, lo_col, up_off, up_col, row_blk;
+  DBuf<Block> blocks;
+  DBuf<double> lo_val, up_val;
+  hipGraphExec_t coarse_graph = nullptr;  // the level sweeps, captured once per factorisation
+  bool direct_coarse = false;             // launch the sweeps directly (inside an enclosing capture)
+  int epb[2] = {0, 0};                    // operator tile (elements per workgroup) for FP64, FP32
+  hipStream_t capture_stream = nullptr;
+  // PCG work
+  DBuf<double> v64[5];
+  DBuf<float> v32[5];
+  DBuf<double> part, sc;
+};
+
+namespace sem {
+
+constexpr int kThreads = 256;
+inline int64_t blocks_of(int64_t n, int t = kThreads) { return n < 1 ? 1 : (n + t - 1) / t; }
+
+// internal operations on a handle (all stream-ordered, no synchronisation)
+template <typename T>
+void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s);
+template <typename T>
+void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s);
+sem_mesh_s* create_mesh(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t n_hex, int order,
+                        const sem_setup_opts* opts);
+int guarded_call(const std::function<int()>& f);
+
+}  // namespace sem

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "sem_device.h"
 #include "sem_internal.h"
 #include "sem_kernels.h"
 
@@ -20,78 +21,11 @@ namespace sem {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-#define SEM_HIP(call)                                                                     \
-  do {                                                                                    \
-    hipError_t err_ = (call);                                                             \
-    if (err_ != hipSuccess)                                                               \
-      throw ::sem::Error{SEM_EHIP, std::string(#call) + ": " + hipGetErrorString(err_)}; \
-  } while (0)
-
-// device buffer owned by a handle
-template <typename T>
-struct DBuf {
-  T* p = nullptr;
-  size_t n = 0;
-  void alloc(size_t count) {
-    release();
-    if (count == 0) return;
-    hipError_t err = hipMalloc((void**)&p, count * sizeof(T));
-    if (err != hipSuccess) {
-      p = nullptr;
-      (void)hipGetLastError();
-      throw Error{SEM_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed"};
-    }
-    n = count;
-  }
-  void upload(const T* h, size_t count) {
-    alloc(count);
-    if (count) SEM_HIP(hipMemcpy(p, h, count * sizeof(T), hipMemcpyHostToDevice));
-  }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  ~DBuf() { release(); }
-};
-
-template <typename TD, typename TS>
-static std::vector<TD> convert(const std::vector<TS>& v) {
-  return std::vector<TD>(v.begin(), v.end());
-}
-
 }  // namespace sem
 
 using namespace sem;
 
-struct sem_mesh_s {
-  HostTables T;
-  bool host_only = false;
-  bool fp32 = true;
-  int device = 0;
-  // numbering / gather
-  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx, order;
-  DBuf<uint8_t> dir, fcount;
-  // operator
-  DBuf<double> G64, D64, w64;
-  DBuf<float> G32, D32, w32;
-  // fine preconditioner
-  DBuf<int32_t> ip, ip_off, ip_slot;
-  DBuf<double> S64, lam64, h64, zP64;
-  DBuf<float> S32, lam32, h32, zP32;
-  // coarse
-  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Ylev, Zv, sinv, ac_val;
-  DBuf<int32_t> ac_off, ac_col, lo_off, lo_col, up_off, up_col;
-  DBuf<double> lo_val, up_val;
-  hipGraphExec_t coarse_graph = nullptr;  // the level sweeps, captured once per factorisation
-  hipStream_t capture_stream = nullptr;
-  // PCG work
-  DBuf<double> v64[5];
-  DBuf<float> v32[5];
-  DBuf<double> part, sc;
-};
-
-namespace {
+namespace sem {
 
 constexpr int kGS = 256;
 
@@ -142,14 +76,62 @@ template <>
 const float* Hp<float>(sem_mesh m) { return m->h32.p; }
 
 // --- operator ---------------------------------------------------------------
+// tile candidates: elements per workgroup, workgroups of at most 1024 lanes;
+// kTileMfma selects the matrix-core kernel (FP64, N = 15)
+constexpr int kTileCandidates[4] = {1, 2, 4, 8};
+constexpr int kTileMfma = 16;
+
+template <int N>
+constexpr bool tile_ok(int epb) {
+  return epb * (N + 1) * (N + 1) <= 1024;
+}
+
+template <int N, typename T, int EPB>
+void launch_ax_tile(sem_mesh m, const T* u, T* y, hipStream_t s) {
+  if constexpr (tile_ok<N>(EPB)) {
+    const HostTables& T_ = m->T;
+    const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
+    hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
+                       Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
+    SEM_HIP(hipGetLastError());
+  } else {
+    throw Error{SEM_EINVAL, "operator tile too large for the order"};
+  }
+}
+
 template <int N, typename T>
 void launch_ax(sem_mesh m, const T* u, T* y, hipStream_t s) {
-  constexpr int EPB = ax_epb<N>();
-  const HostTables& T_ = m->T;
-  const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
-  hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
-                     Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
-  SEM_HIP(hipGetLastError());
+  const int epb = m->epb[std::is_same<T, double>::value ? 0 : 1];
+  if (epb == kTileMfma) {
+    if constexpr (N == 15 && std::is_same<T, double>::value) {
+      const HostTables& T_ = m->T;
+      hipLaunchKernelGGL(ax_mfma15_kernel, dim3((unsigned)xcd_grid(T_.E)), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
+                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
+      SEM_HIP(hipGetLastError());
+      return;
+    } else {
+      throw Error{SEM_EINVAL, "the matrix-core operator exists for FP64 at N = 15"};
+    }
+  }
+  switch (epb > 0 ? epb : ax_epb<N>()) {
+    case 1: launch_ax_tile<N, T, 1>(m, u, y, s); break;
+    case 2: launch_ax_tile<N, T, 2>(m, u, y, s); break;
+    case 4: launch_ax_tile<N, T, 4>(m, u, y, s); break;
+    case 8: launch_ax_tile<N, T, 8>(m, u, y, s); break;
+    default: throw Error{SEM_EINVAL, "operator tile"};
+  }
+}
+
+int default_tile(int N) {
+  switch (N) {
+#define CASE(NN) \
+  case NN:       \
+    return ax_epb<NN>();
+    CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+    CASE(15)
+#undef CASE
+  }
+  return 1;
 }
 
 template <typename T>
@@ -214,11 +196,13 @@ void fdm_and_restrict(sem_mesh m, const T* r, bool fine, bool coarse, hipStream_
   }
 }
 
-size_t max_level(const HostTables& T) {
+size_t max_block(const HostTables& T) {
   size_t mx = 0;
-  for (auto& L : T.levels) mx = std::max<size_t>(mx, L.size);
+  for (auto& B : T.blocks) mx = std::max<size_t>(mx, B.size);
   return mx;
 }
+
+
 
 // Rlev (level order) -> Zv (vertex order): block LDL^T sweeps
 void coarse_sweeps(sem_mesh m, hipStream_t s) {
@@ -229,7 +213,7 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
     hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
                        m->Rlev.p, m->Wlev.p, m->lo_off.p, m->lo_col.p, m->lo_val.p, L.off, L.size, 1);
     hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Wlev.p, m->Wlev.p, m->Ylev.p,
-                       m->sinv.p + L.sinv, L.off, L.size, 0);
+                       m->sinv.p, m->blocks.p, m->row_blk.p, L.off, L.size, 0);
     SEM_HIP(hipGetLastError());
   }
   for (int k = nl - 1; k >= 0; --k) {
@@ -241,7 +225,7 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
       hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
                          m->Rlev.p, m->Xlev.p, m->up_off.p, m->up_col.p, m->up_val.p, L.off, L.size, 0);
       hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Xlev.p, m->Wlev.p,
-                         m->Ylev.p, m->sinv.p + L.sinv, L.off, L.size, 1);
+                         m->Ylev.p, m->sinv.p, m->blocks.p, m->row_blk.p, L.off, L.size, 1);
     }
     SEM_HIP(hipGetLastError());
   }
@@ -257,6 +241,10 @@ void release_coarse_graph(sem_mesh m) {
 
 // capture the sweeps once (on a private stream) and replay them on the caller's stream
 void coarse_solve_levels(sem_mesh m, hipStream_t s) {
+  if (m->direct_coarse) {
+    coarse_sweeps(m, s);
+    return;
+  }
   if (!m->coarse_graph) {
     if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
@@ -301,7 +289,9 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
   SEM_HIP(hipGetLastError());
 }
 
-// --- coarse factorisation (set-up): Sinv_k = S_k^{-1}, S_k the Schur complements
+// --- coarse factorisation (set-up): per block b of level k, the Schur
+// complement S_b = A_bb - A_{b,p} Sinv_p A_{p,b} (p: the component's block in
+// level k-1) and its dense inverse Sinv_b
 void factor_coarse(sem_mesh m) {
   HostTables& T = m->T;
   release_coarse_graph(m);
@@ -315,6 +305,8 @@ void factor_coarse(sem_mesh m) {
   m->up_col.upload(T.up_col.data(), T.up_col.size());
   m->up_val.upload(T.up_val.data(), T.up_val.size());
   m->cidx.upload(T.cidx.data(), T.cidx.size());
+  m->row_blk.upload(T.row_blk.data(), T.row_blk.size());
+  m->blocks.upload(T.blocks.data(), T.blocks.size());
   const size_t nc = std::max<int64_t>(T.nc, 1);
   m->Rlev.alloc(nc);
   m->Wlev.alloc(nc);
@@ -324,12 +316,10 @@ void factor_coarse(sem_mesh m) {
     m->sinv.release();
     return;
   }
-  // dense inverse Schur complements are kept per level: bound their size
-  if (max_level(T) > 16384)
-    throw Error{SEM_EUNSUPPORTED, "coarse level of " + std::to_string(max_level(T)) + " vertices exceeds 16384"};
-  int64_t pool = 0;
-  for (auto& L : T.levels) pool += L.size * L.size;
-  m->sinv.alloc(pool);
+  // dense inverse Schur complements are kept per block: bound their size
+  if (max_block(T) > 16384)
+    throw Error{SEM_EUNSUPPORTED, "coarse block of " + std::to_string(max_block(T)) + " vertices exceeds 16384"};
+  m->sinv.alloc(T.sinv_size);
   rocblas_handle hb;
   if (rocblas_create_handle(&hb) != rocblas_status_success) throw Error{SEM_EHIP, "rocblas_create_handle failed"};
   std::unique_ptr<std::remove_pointer<rocblas_handle>::type, decltype(&rocblas_destroy_handle)> guard(
@@ -337,13 +327,13 @@ void factor_coarse(sem_mesh m) {
   DBuf<double> Bd, Td;
   DBuf<rocblas_int> info;
   info.alloc(1);
-  const size_t mx = max_level(T);
+  const size_t mx = max_block(T);
   Bd.alloc(mx * mx);
   Td.alloc(mx * mx);
   std::vector<double> dense;
-  for (size_t k = 0; k < T.levels.size(); ++k) {
-    const Level& L = T.levels[k];
-    // A_kk, column-major (symmetric)
+  for (size_t b = 0; b < T.blocks.size(); ++b) {
+    const Block& L = T.blocks[b];
+    // A_bb, column-major (symmetric)
     dense.assign(L.size * L.size, 0.0);
     for (int64_t r = 0; r < L.size; ++r)
       for (int32_t q = T.ac_off[L.off + r]; q < T.ac_off[L.off + r + 1]; ++q) {
@@ -352,9 +342,9 @@ void factor_coarse(sem_mesh m) {
       }
     double* Sk = m->sinv.p + L.sinv;
     SEM_HIP(hipMemcpy(Sk, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (k > 0) {
-      const Level& P = T.levels[k - 1];
-      // B = A_{k-1,k}: rows of level k-1, columns of level k (column-major, ld = |P|)
+    if (L.prev >= 0) {
+      const Block& P = T.blocks[L.prev];
+      // B = A_{p,b}: rows of block p, columns of block b (column-major, ld = |p|)
       dense.assign(P.size * L.size, 0.0);
       for (int64_t r = 0; r < P.size; ++r)
         for (int32_t q = T.ac_off[P.off + r]; q < T.ac_off[P.off + r + 1]; ++q) {
@@ -364,11 +354,11 @@ void factor_coarse(sem_mesh m) {
       SEM_HIP(hipMemcpy(Bd.p, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
       const double one = 1.0, zero = 0.0, mone = -1.0;
       const rocblas_int pn = (rocblas_int)P.size, ln = (rocblas_int)L.size;
-      // T = Sinv_{k-1} B
+      // T = Sinv_p B
       if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, pn, ln, pn, &one,
                         m->sinv.p + P.sinv, pn, Bd.p, pn, &zero, Td.p, pn) != rocblas_status_success)
         throw Error{SEM_EHIP, "rocblas_dgemm failed"};
-      // S_k = A_kk - B^T T
+      // S_b = A_bb - B^T T
       if (rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, ln, ln, pn, &mone, Bd.p, pn, Td.p,
                         pn, &one, Sk, ln) != rocblas_status_success)
         throw Error{SEM_EHIP, "rocblas_dgemm failed"};
@@ -651,7 +641,119 @@ int need_device(sem_mesh m) {
   return SEM_OK;
 }
 
-}  // namespace
+template void apply_A<double>(sem_mesh, const double*, double*, hipStream_t);
+template void apply_A<float>(sem_mesh, const float*, float*, hipStream_t);
+template void precond<double>(sem_mesh, const double*, double*, int, hipStream_t);
+template void precond<float>(sem_mesh, const float*, float*, int, hipStream_t);
+
+// Autotuner of the operator tile: time each candidate (elements per
+// workgroup) on this mesh and keep the fastest; results keyed by
+// (architecture, order, dtype, element-count bucket) in an optional text cache.
+template <typename T>
+int tune_tile(sem_mesh m) {
+  const int N = m->T.N;
+  std::vector<int> cands;
+  for (int c : kTileCandidates)
+    if (c * (N + 1) * (N + 1) <= 1024 && c * (N + 1) * (N + 1) >= 16) cands.push_back(c);
+  if (N == 15 && std::is_same<T, double>::value) cands.push_back(kTileMfma);
+  if (cands.size() <= 1) return cands.empty() ? 1 : cands[0];
+  DBuf<T> u, y;
+  u.alloc(m->T.n_global);
+  y.alloc(m->T.n_global);
+  hipLaunchKernelGGL((fill_kernel<T>), dim3(grid_stride_blocks(m->T.n_global)), dim3(kGS), 0, 0, u.p, T(1),
+                     m->T.n_global);
+  hipEvent_t a, b;
+  SEM_HIP(hipEventCreate(&a));
+  SEM_HIP(hipEventCreate(&b));
+  int best = cands[0];
+  float best_ms = 1e30f;
+  const int idx = std::is_same<T, double>::value ? 0 : 1;
+  for (int c : cands) {
+    m->epb[idx] = c;
+    apply_A_elements<T>(m, u.p, y.p, 0);
+    SEM_HIP(hipEventRecord(a, 0));
+    for (int r = 0; r < 3; ++r) apply_A_elements<T>(m, u.p, y.p, 0);
+    SEM_HIP(hipEventRecord(b, 0));
+    SEM_HIP(hipEventSynchronize(b));
+    float ms = 0.f;
+    SEM_HIP(hipEventElapsedTime(&ms, a, b));
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+std::string tune_key(sem_mesh m, int dtype) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, m->device) != hipSuccess) return "";
+  int bucket = 0;
+  for (int64_t e = m->T.E; e > 1; e >>= 2) ++bucket;  // element count, base-4 buckets
+  return std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':')) + " N=" +
+         std::to_string(m->T.N) + " dtype=" + std::to_string(dtype) + " ebucket=" + std::to_string(bucket);
+}
+
+void autotune(sem_mesh m, const char* cache) {
+  for (int d = 0; d < (m->fp32 ? 2 : 1); ++d) {
+    const std::string key = tune_key(m, d);
+    int found = 0;
+    if (cache && !key.empty()) {
+      if (FILE* f = std::fopen(cache, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+          std::string l(line);
+          const size_t p = l.rfind(" epb=");
+          if (p != std::string::npos && l.compare(0, p, key) == 0) found = std::atoi(l.c_str() + p + 5);
+        }
+        std::fclose(f);
+      }
+    }
+    if (found == 1 || found == 2 || found == 4 || found == 8 || (found == kTileMfma && d == 0 && m->T.N == 15)) {
+      m->epb[d] = found;
+      continue;
+    }
+    m->epb[d] = d == 0 ? tune_tile<double>(m) : tune_tile<float>(m);
+    if (cache && !key.empty())
+      if (FILE* f = std::fopen(cache, "a")) {
+        std::fprintf(f, "%s epb=%d\n", key.c_str(), m->epb[d]);
+        std::fclose(f);
+      }
+  }
+  SEM_HIP(hipDeviceSynchronize());
+}
+
+sem_mesh_s* create_mesh(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t n_hex, int order,
+                        const sem_setup_opts* opts) {
+  if (!vtx || !hex || n_vtx <= 0 || n_hex <= 0) throw Error{SEM_EINVAL, "NULL or empty mesh input"};
+  if (order < 2 || order > 15) throw Error{SEM_EUNSUPPORTED, "order must be in 2..15"};
+  sem_setup_opts d;
+  sem_default_setup_opts(&d);
+  if (!opts) opts = &d;
+  auto m = std::make_unique<sem_mesh_s>();
+  m->host_only = opts->host_only != 0;
+  m->fp32 = opts->build_fp32 != 0;
+  m->device = opts->device;
+  HostTables& T = m->T;
+  build_reference(T, order);
+  build_numbering(T, hex, n_hex, n_vtx);
+  build_geometry(T, vtx, hex);
+  build_patches(T, hex);
+  build_coarse_matrices(T, vtx, hex);
+  build_coarse_levels(T);
+  m->epb[0] = m->epb[1] = default_tile(order);
+  if (!m->host_only) {
+    upload_all(m.get());
+    if (opts->autotune) autotune(m.get(), opts->tune_cache);
+  }
+  return m.release();
+}
+
+int guarded_call(const std::function<int()>& f) { return guarded(f); }
+
+}  // namespace sem
 
 // ============================================================================
 // C ABI
@@ -663,6 +765,27 @@ void sem_default_setup_opts(sem_setup_opts* o) {
   o->device = 0;
   o->host_only = 0;
   o->build_fp32 = 1;
+  o->autotune = 1;
+  o->tune_cache = nullptr;
+}
+
+int sem_mesh_set_tile(sem_mesh m, int dtype, int epb) {
+  if (!m || (dtype != SEM_F64 && dtype != SEM_F32)) return SEM_EINVAL;
+  const int N = m->T.N;
+  const bool ok = (epb == 1 || epb == 2 || epb == 4 || epb == 8) ? epb * (N + 1) * (N + 1) <= 1024
+                                                                  : (epb == kTileMfma && N == 15 && dtype == SEM_F64);
+  if (!ok) {
+    set_error("tile not available for this order and dtype");
+    return SEM_EINVAL;
+  }
+  m->epb[dtype == SEM_F64 ? 0 : 1] = epb;
+  return SEM_OK;
+}
+
+int sem_mesh_tile(sem_mesh m, int dtype, int* epb) {
+  if (!m || !epb || (dtype != SEM_F64 && dtype != SEM_F32)) return SEM_EINVAL;
+  *epb = m->epb[dtype == SEM_F64 ? 0 : 1];
+  return SEM_OK;
 }
 
 void sem_default_solve_opts(sem_solve_opts* o) {
@@ -682,25 +805,9 @@ const char* sem_last_error(void) { return g_last_error.c_str(); }
 int sem_mesh_setup(const double* vtx, int64_t n_vtx, const int64_t* hex, int64_t n_hex, int order,
                    const sem_setup_opts* opts, sem_mesh* out) {
   return guarded([&]() -> int {
-    if (!out || !vtx || !hex || n_vtx <= 0 || n_hex <= 0) throw Error{SEM_EINVAL, "NULL or empty mesh input"};
+    if (!out) throw Error{SEM_EINVAL, "NULL output handle"};
     *out = nullptr;
-    if (order < 2 || order > 15) throw Error{SEM_EUNSUPPORTED, "order must be in 2..15"};
-    sem_setup_opts d;
-    sem_default_setup_opts(&d);
-    if (!opts) opts = &d;
-    auto m = std::make_unique<sem_mesh_s>();
-    m->host_only = opts->host_only != 0;
-    m->fp32 = opts->build_fp32 != 0;
-    m->device = opts->device;
-    HostTables& T = m->T;
-    build_reference(T, order);
-    build_numbering(T, hex, n_hex, n_vtx);
-    build_geometry(T, vtx, hex);
-    build_patches(T, hex);
-    build_coarse_matrices(T, vtx, hex);
-    build_coarse_levels(T);
-    if (!m->host_only) upload_all(m.get());
-    *out = m.release();
+    *out = create_mesh(vtx, n_vtx, hex, n_hex, order, opts);
     return SEM_OK;
   });
 }

@@ -40,10 +40,23 @@ inline int32_t pack_coef(int ai, int aj, int ak) {
   return (ai & 0x3FF) | ((aj & 0x3FF) << 10) | ((ak & 0x3FF) << 20);
 }
 
+// Coarse levels: BFS levels of each connected component of the free-vertex
+// graph, merged by level index.  Level l is one contiguous range of coarse
+// indices made of one block per component; a block couples only to the block
+// of the same component in the neighbouring levels.
 struct Level {
-  int64_t off;   // first coarse index of the level
-  int64_t size;  // number of free vertices in the level
-  int64_t sinv;  // offset of its dense inverse Schur complement in the Sinv pool
+  int64_t off;         // first coarse index of the level
+  int64_t size;        // number of free vertices in the level
+  int32_t blk_begin;   // its blocks [blk_begin, blk_end)
+  int32_t blk_end;
+};
+
+struct Block {
+  int64_t off;   // first coarse index
+  int64_t size;  // rows
+  int64_t sinv;  // offset of its dense inverse Schur complement in the pool
+  int32_t prev;  // block of the same component in the previous level, or -1
+  int32_t pad;
 };
 
 struct HostTables {
@@ -82,6 +95,9 @@ struct HostTables {
   std::vector<int32_t> cidx;             // [V] coarse index or -1 (Dirichlet vertex)
   int64_t nc = 0;                        // number of free vertices
   std::vector<Level> levels;
+  std::vector<Block> blocks;
+  std::vector<int32_t> row_blk;          // [nc] block of each coarse row
+  int64_t sinv_size = 0;
   std::vector<int32_t> ac_off, ac_col;   // CSR of A_c in level order
   std::vector<double> ac_val;
   std::vector<int32_t> lo_off, lo_col, up_off, up_col;  // couplings to the previous / next level

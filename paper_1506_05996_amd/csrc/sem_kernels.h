@@ -141,6 +141,124 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
 }
 
 // ---------------------------------------------------------------------------
+// Operator at N = 15 on FP64 matrix cores (v_mfma_f64_16x16x4f64).  One
+// workgroup of four waves per element (16^3 nodes).  MFMA operand layout for
+// a 16x16 product with K = 4: lane l supplies A[l%16][l/16] and B[l/16][l%16]
+// and receives D[4(l/16)+r][l%16], r = 0..3.
+//   1. zeta derivative  UT = D (16x16) x U (16 x 256 columns (j,i)), 4 tiles per wave
+//   2. per plane k (4 planes per wave): UR = U_k D^T, US = D U_k, the factors
+//      G at the lane's 4 nodes, A, B, C; then W_k = A_k D + D^T B_k
+//   3. zeta transpose  W += D^T (16x16) x C (16 x 256), 4 tiles per wave, and the
+//      results go to y (element interiors) or the work array (shared nodes).
+// D is held in registers in both operand layouts (4 + 4 doubles per lane).
+typedef double sem_d4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* __restrict__ w,
+                 const double* __restrict__ G, const int32_t* __restrict__ rec, const double* __restrict__ Dg,
+                 const uint8_t* __restrict__ dir, const int32_t* __restrict__ order, int64_t E) {
+  constexpr int N = 15, n1 = 16, P = 256, NN = 4096;
+  __shared__ double sU[NN];        // u, later the xi/eta part of the result
+  __shared__ double sT[NN];        // zeta derivative of u, later C
+  __shared__ double sS[4][2][P];   // per-wave A_k, B_k
+  const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
+  const int lr = l & 15, lq = l >> 4;
+  const int64_t pos = xcd_position(blockIdx.x, E);
+  if (pos >= E) return;  // whole workgroup
+  const int64_t e = order[pos];
+  // gather: lane tid owns the k-pencil of node (i, j) = (tid % 16, tid / 16)
+  {
+    const int i0 = tid & 15, j0 = tid >> 4;
+    const int cx = node_class(i0, N), cy = node_class(j0, N);
+#pragma unroll 4
+    for (int k = 0; k < n1; ++k) {
+      const NodeAddr a = node_addr(rec, e, cx, cy, k, i0, j0, N);
+      sU[k * P + tid] = u[a.g];
+    }
+  }
+  double DA[4], DB[4];  // DA[s] = D[lr][4s+lq] (A layout of D), DB[s] = D[4s+lq][lr] (B layout)
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    DA[s] = Dg[lr * n1 + 4 * s + lq];
+    DB[s] = Dg[(4 * s + lq) * n1 + lr];
+  }
+  __syncthreads();
+  // 1. UT[k'][col] = sum_k D[k'][k] U[k][col]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = wave * 4 + q;
+    sem_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(DA[s], sU[(4 * s + lq) * P + t * 16 + lr], acc, 0, 0, 0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sT[(4 * lq + r) * P + t * 16 + lr] = acc[r];
+  }
+  __syncthreads();
+  // 2. planes
+  const double* Ge = G + e * 6 * NN;
+  sem_d4 W[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = wave * 4 + q;
+    const double* Uk = sU + k * P;
+    sem_d4 ur = {0.0, 0.0, 0.0, 0.0}, us = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(Uk[lr * n1 + 4 * s + lq], DA[s], ur, 0, 0, 0);  // U_k D^T
+      us = __builtin_amdgcn_mfma_f64_16x16x4f64(DA[s], Uk[(4 * s + lq) * n1 + lr], us, 0, 0, 0);  // D U_k
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int node = k * P + (4 * lq + r) * n1 + lr;
+      const double ut = sT[node];
+      const double g0 = Ge[0 * NN + node], g1 = Ge[1 * NN + node], g2 = Ge[2 * NN + node];
+      const double g3 = Ge[3 * NN + node], g4 = Ge[4 * NN + node], g5 = Ge[5 * NN + node];
+      const double A = g0 * ur[r] + g1 * us[r] + g2 * ut;
+      const double B = g1 * ur[r] + g3 * us[r] + g4 * ut;
+      const double C = g2 * ur[r] + g4 * us[r] + g5 * ut;
+      sS[wave][0][(4 * lq + r) * n1 + lr] = A;
+      sS[wave][1][(4 * lq + r) * n1 + lr] = B;
+      sT[node] = C;  // plane k of the zeta derivative is no longer needed
+    }
+    __syncthreads();
+    sem_d4 wk = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      wk = __builtin_amdgcn_mfma_f64_16x16x4f64(sS[wave][0][lr * n1 + 4 * s + lq], DB[s], wk, 0, 0, 0);  // A_k D
+      wk = __builtin_amdgcn_mfma_f64_16x16x4f64(DB[s], sS[wave][1][(4 * s + lq) * n1 + lr], wk, 0, 0, 0);  // D^T B_k
+    }
+    W[q] = wk;
+    __syncthreads();
+  }
+  // xi/eta part of the result into sU (u is no longer read)
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sU[(wave * 4 + q) * P + (4 * lq + r) * n1 + lr] = W[q][r];
+  __syncthreads();
+  // 3. zeta transpose and output: tile t = row j of every plane
+  const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int t = wave * 4 + q;
+    sem_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(DB[s], sT[(4 * s + lq) * P + t * 16 + lr], acc, 0, 0, 0);
+    const int j = t, i = lr, cx = node_class(i, N), cy = node_class(j, N);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = 4 * lq + r;
+      const double v = acc[r] + sU[k * P + j * n1 + i];
+      const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
+      if (a.flags & kFlagInterior)
+        y[a.g] = (masked_interior && dir[a.g]) ? 0.0 : v;
+      else
+        w[a.w] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Gather of the shared nodes (eq. (gather)): one lane per shared global node,
 // copies summed in ascending element order, Dirichlet nodes zeroed.
 // ---------------------------------------------------------------------------
@@ -395,19 +513,23 @@ coarse_couple_kernel(double* __restrict__ Y, const double* __restrict__ R, const
   if (sub == 0) Y[row] = forward ? R[row] - s : s;
 }
 
-// Out_k = (sub ? W_k - S Y_k : S Y_k), S dense symmetric lsize x lsize: one
-// workgroup per row, its four waves take one quarter of the columns each with
-// eight independent partial sums per lane.
+// Out_r = (sub ? W_r - (S_b Y_b)_r : (S_b Y_b)_r) for the rows r of one level,
+// S_b the dense symmetric inverse Schur complement of the row's block: one
+// workgroup per row, its four waves take one quarter of the block's columns
+// each with eight independent partial sums per lane.
 __global__ void __launch_bounds__(256)
 coarse_gemv_kernel(double* __restrict__ Out, const double* __restrict__ W, const double* __restrict__ Y,
-                   const double* __restrict__ S, int64_t loff, int64_t lsize, int sub) {
+                   const double* __restrict__ Spool, const Block* __restrict__ blocks,
+                   const int32_t* __restrict__ row_blk, int64_t loff, int64_t lsize, int sub) {
   __shared__ double part[4];
-  const int64_t row = blockIdx.x;
-  if (row >= lsize) return;
+  if ((int64_t)blockIdx.x >= lsize) return;
+  const int64_t row = loff + blockIdx.x;
+  const Block B = blocks[row_blk[row]];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t q4 = (lsize + 3) / 4, c0 = wave * q4, c1 = c0 + q4 < lsize ? c0 + q4 : lsize;
-  const double* Sr = S + row * lsize;
-  const double* y = Y + loff;
+  const int64_t n = B.size;
+  const int64_t q4 = (n + 3) / 4, c0 = wave * q4, c1 = c0 + q4 < n ? c0 + q4 : n;
+  const double* Sr = Spool + B.sinv + (row - B.off) * n;
+  const double* y = Y + B.off;
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t c = c0 + lane;
   for (; c + 448 < c1; c += 512) {
@@ -421,7 +543,7 @@ coarse_gemv_kernel(double* __restrict__ Out, const double* __restrict__ W, const
   __syncthreads();
   if (threadIdx.x == 0) {
     const double t = (part[0] + part[1]) + (part[2] + part[3]);
-    Out[loff + row] = sub ? W[loff + row] - t : t;
+    Out[row] = sub ? W[row] - t : t;
   }
 }
 

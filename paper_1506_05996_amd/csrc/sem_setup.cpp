@@ -880,7 +880,27 @@ void build_coarse_levels(HostTables& T) {
   }
   std::vector<char> freev(V);
   for (int64_t v = 0; v < V; ++v) freev[v] = T.dir[v] == 0;
-  // coordinates of the vertex nodes, longest extent of the mesh
+  // connected components of the free-vertex graph (a batch of meshes is one
+  // mesh with several components; they never couple)
+  std::vector<int32_t> comp(V, -1);
+  int32_t ncomp = 0;
+  for (int64_t v0 = 0; v0 < V; ++v0) {
+    if (!freev[v0] || comp[v0] >= 0) continue;
+    std::vector<int64_t> stack{v0};
+    comp[v0] = ncomp;
+    while (!stack.empty()) {
+      int64_t v = stack.back();
+      stack.pop_back();
+      for (int64_t w : adj[v])
+        if (freev[w] && comp[w] < 0) {
+          comp[w] = ncomp;
+          stack.push_back(w);
+        }
+    }
+    ++ncomp;
+  }
+  // per component: BFS levels from the free vertices nearest the low end of
+  // the mesh's longest axis (plane-shaped levels on box meshes)
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < V; ++v)
     for (int r = 0; r < 3; ++r) {
@@ -890,29 +910,29 @@ void build_coarse_levels(HostTables& T) {
   int ax = 0;
   for (int r = 1; r < 3; ++r)
     if (hi[r] - lo[r] > hi[ax] - lo[ax]) ax = r;
-  double hmean = 0.0;
-  for (int64_t e = 0; e < E; ++e) hmean += T.h[e * 3 + ax];
-  hmean /= std::max<int64_t>(1, E);
-  // multi-source BFS from the free vertices nearest the low end of that axis
+  std::vector<double> hsum(ncomp, 0.0), xmin(ncomp, 1e300);
+  std::vector<int64_t> hcnt(ncomp, 0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int p = 0; p < 8; ++p) {
+      const int32_t c = comp[vid[e * 8 + p]];
+      if (c >= 0) {
+        hsum[c] += T.h[e * 3 + ax];
+        hcnt[c]++;
+        break;
+      }
+    }
+  for (int64_t v = 0; v < V; ++v)
+    if (comp[v] >= 0) xmin[comp[v]] = std::min(xmin[comp[v]], T.xN[v * 3 + ax]);
   std::vector<int32_t> level(V, -1);
-  std::vector<int64_t> order;
-  order.reserve(V);
-  std::vector<int64_t> lvl_start;
-  int64_t nfree = 0;
-  for (int64_t v = 0; v < V; ++v) nfree += freev[v];
-  int cur = 0;
-  while ((int64_t)order.size() < nfree) {
-    double xmin = 1e300;
-    for (int64_t v = 0; v < V; ++v)
-      if (freev[v] && level[v] < 0) xmin = std::min(xmin, T.xN[v * 3 + ax]);
+  int32_t nlev = 0;
+  for (int32_t c = 0; c < ncomp; ++c) {
+    const double hm = hcnt[c] ? hsum[c] / hcnt[c] : 0.0;
     std::vector<int64_t> front;
     for (int64_t v = 0; v < V; ++v)
-      if (freev[v] && level[v] < 0 && T.xN[v * 3 + ax] <= xmin + 0.5 * hmean) front.push_back(v);
+      if (comp[v] == c && T.xN[v * 3 + ax] <= xmin[c] + 0.5 * hm) front.push_back(v);
+    int32_t cur = 0;
+    for (int64_t v : front) level[v] = 0;
     while (!front.empty()) {
-      lvl_start.push_back((int64_t)order.size());
-      for (int64_t v : front) level[v] = cur;
-      std::sort(front.begin(), front.end());
-      for (int64_t v : front) order.push_back(v);
       std::vector<int64_t> next;
       for (int64_t v : front)
         for (int64_t w : adj[v])
@@ -925,21 +945,51 @@ void build_coarse_levels(HostTables& T) {
       ++cur;
       front.swap(next);
     }
+    nlev = std::max(nlev, cur);
   }
-  lvl_start.push_back((int64_t)order.size());
+  // coarse order: by (level, component, vertex id); a level is one contiguous
+  // range, made of one block per component
+  std::vector<int64_t> order;
+  for (int64_t v = 0; v < V; ++v)
+    if (freev[v]) order.push_back(v);
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    if (level[a] != level[b]) return level[a] < level[b];
+    if (comp[a] != comp[b]) return comp[a] < comp[b];
+    return a < b;
+  });
   T.nc = (int64_t)order.size();
   T.cidx.assign(V, -1);
   for (int64_t p = 0; p < T.nc; ++p) T.cidx[order[p]] = (int32_t)p;
   T.levels.clear();
+  T.blocks.clear();
+  T.row_blk.assign(T.nc, -1);
+  std::vector<int32_t> last_blk(ncomp, -1);
   int64_t pool = 0;
-  for (size_t l = 0; l + 1 < lvl_start.size(); ++l) {
+  for (int64_t p = 0; p < T.nc;) {
+    const int32_t l = level[order[p]];
     Level L;
-    L.off = lvl_start[l];
-    L.size = lvl_start[l + 1] - lvl_start[l];
-    L.sinv = pool;
-    pool += L.size * L.size;
+    L.off = p;
+    L.blk_begin = (int32_t)T.blocks.size();
+    while (p < T.nc && level[order[p]] == l) {
+      const int32_t c = comp[order[p]];
+      Block B;
+      B.off = p;
+      while (p < T.nc && level[order[p]] == l && comp[order[p]] == c) {
+        T.row_blk[p] = (int32_t)T.blocks.size();
+        ++p;
+      }
+      B.size = p - B.off;
+      B.sinv = pool;
+      pool += B.size * B.size;
+      B.prev = last_blk[c];
+      last_blk[c] = (int32_t)T.blocks.size();
+      T.blocks.push_back(B);
+    }
+    L.size = p - L.off;
+    L.blk_end = (int32_t)T.blocks.size();
     T.levels.push_back(L);
   }
+  T.sinv_size = pool;
   // CSR of A_c in level order (assembled from the corner matrices, element order)
   std::vector<std::vector<std::pair<int32_t, double>>> rows(T.nc);
   for (int64_t e = 0; e < E; ++e)
@@ -981,6 +1031,10 @@ void build_coarse_levels(HostTables& T) {
   for (int64_t r = 0; r < T.nc; ++r) {
     const Level& L = T.levels[lev_of[r]];
     for (int32_t q = T.ac_off[r]; q < T.ac_off[r + 1]; ++q) {
+      // components never couple, and levels couple only to neighbours
+      if (T.row_blk[T.ac_col[q]] != T.row_blk[r] && T.blocks[T.row_blk[T.ac_col[q]]].prev != T.row_blk[r] &&
+          T.blocks[T.row_blk[r]].prev != T.row_blk[T.ac_col[q]])
+        throw Error{SEM_EMESH, "coarse level structure broken"};
       const int32_t c = T.ac_col[q];
       if (c < L.off) {
         T.lo_col.push_back(c);

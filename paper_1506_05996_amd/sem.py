@@ -35,12 +35,14 @@ EXPORTS = [
     "sem_mesh_sizes", "sem_mesh_numbering", "sem_mesh_gs_csr", "sem_mesh_patch_table",
     "sem_mesh_node_coords", "sem_mesh_lumped_mass", "sem_mesh_boundary_mask", "sem_mesh_geometry",
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
-    "sem_time_apply_A", "sem_last_error",
+    "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
+    "sem_batch_destroy",
 ]
 
 
 class SetupOpts(ctypes.Structure):
-    _fields_ = [("device", ctypes.c_int), ("host_only", ctypes.c_int), ("build_fp32", ctypes.c_int)]
+    _fields_ = [("device", ctypes.c_int), ("host_only", ctypes.c_int), ("build_fp32", ctypes.c_int),
+                ("autotune", ctypes.c_int), ("tune_cache", ctypes.c_char_p)]
 
 
 class SolveOpts(ctypes.Structure):
@@ -77,6 +79,13 @@ _lib.sem_pcg_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POI
 _lib.sem_time_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
 _lib.sem_last_error.restype = ctypes.c_char_p
+_lib.sem_batch_setup.argtypes = [ctypes.c_int, _p, _p, _p, _p, _p, ctypes.POINTER(SetupOpts), ctypes.POINTER(_p)]
+_lib.sem_batch_sizes.argtypes = [_p, _p]
+_lib.sem_batch_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), _p, _p]
+_lib.sem_batch_destroy.argtypes = [_p]
+_lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
+TILE_MFMA = 16
 
 
 class SemError(RuntimeError):
@@ -121,12 +130,14 @@ def default_solve_opts(**kw) -> SolveOpts:
 class Mesh:
     """Owning wrapper of a ``sem_mesh`` handle."""
 
-    def __init__(self, vtx, hexes, order, host_only=False, device=0, build_fp32=True):
+    def __init__(self, vtx, hexes, order, host_only=False, device=0, build_fp32=True, autotune=True,
+                 tune_cache=None):
         vtx = np.ascontiguousarray(vtx, dtype=np.float64)
         hexes = np.ascontiguousarray(hexes, dtype=np.int64)
         if vtx.ndim != 2 or vtx.shape[1] != 3 or hexes.ndim != 2 or hexes.shape[1] != 8:
             raise ValueError("vtx must be [V,3] and hexes [E,8]")
-        opts = SetupOpts(device=device, host_only=int(host_only), build_fp32=int(build_fp32))
+        opts = SetupOpts(device=device, host_only=int(host_only), build_fp32=int(build_fp32),
+                         autotune=int(autotune), tune_cache=tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
         _check(_lib.sem_mesh_setup(_ptr(vtx), vtx.shape[0], _ptr(hexes), hexes.shape[0], int(order),
                                    ctypes.byref(opts), ctypes.byref(h)))
@@ -223,6 +234,15 @@ class Mesh:
         _check(_lib.sem_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), _stream(stream)))
         return y
 
+    def tile(self, dtype=SEM_F64) -> int:
+        """Elements per workgroup the operator kernel uses for dtype."""
+        v = ctypes.c_int()
+        _check(_lib.sem_mesh_tile(self._h, int(dtype), ctypes.byref(v)))
+        return v.value
+
+    def set_tile(self, epb, dtype=SEM_F64):
+        _check(_lib.sem_mesh_set_tile(self._h, int(dtype), int(epb)))
+
     def time_apply_A(self, u, y, reps, stream=None):
         """Mean (element kernel, gather kernel) durations in ms over `reps` applies."""
         self._check_vec(u)
@@ -273,6 +293,65 @@ class Mesh:
         if status != SEM_OK and (status != SEM_ENOCONV or raise_on_noconv):
             raise SemError(status, last_error() + f" ({info})")
         return x, info
+
+
+class Batch:
+    """Owning wrapper of a ``sem_batch`` handle: independent meshes solved together."""
+
+    def __init__(self, meshes, device=0, build_fp32=True, autotune=True, tune_cache=None):
+        """meshes: list of (vtx [V,3], hexes [E,8], order)."""
+        self._keep = []
+        n = len(meshes)
+        vp, hp = (ctypes.c_void_p * n)(), (ctypes.c_void_p * n)()
+        nv, nh, orders = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int * n)()
+        for i, (vtx, hexes, order) in enumerate(meshes):
+            vtx = np.ascontiguousarray(vtx, dtype=np.float64)
+            hexes = np.ascontiguousarray(hexes, dtype=np.int64)
+            self._keep += [vtx, hexes]
+            vp[i], hp[i] = vtx.ctypes.data, hexes.ctypes.data
+            nv[i], nh[i], orders[i] = vtx.shape[0], hexes.shape[0], int(order)
+        opts = SetupOpts(device=device, host_only=0, build_fp32=int(build_fp32), autotune=int(autotune),
+                         tune_cache=tune_cache.encode() if tune_cache else None)
+        h = ctypes.c_void_p()
+        _check(_lib.sem_batch_setup(n, ctypes.cast(vp, _p), ctypes.cast(nv, _p), ctypes.cast(hp, _p),
+                                    ctypes.cast(nh, _p), ctypes.cast(orders, _p), ctypes.byref(opts),
+                                    ctypes.byref(h)))
+        self._h = h
+        self.n = n
+        ng = (ctypes.c_int64 * n)()
+        _check(_lib.sem_batch_sizes(h, ctypes.cast(ng, _p)))
+        self.n_global = list(ng)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.sem_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def solve(self, bs, xs=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-8, max_iter=1000, inner_rtol=1e-3,
+              max_outer=20, check_every=1, stream=None, raise_on_noconv=True):
+        import torch
+        if len(bs) != self.n:
+            raise ValueError("one right-hand side per instance")
+        if xs is None:
+            xs = [torch.zeros_like(b) for b in bs]
+        bp, xp = (ctypes.c_void_p * self.n)(), (ctypes.c_void_p * self.n)()
+        for i, (b, x) in enumerate(zip(bs, xs)):
+            if b.dtype != torch.float64 or not b.is_cuda or b.numel() != self.n_global[i]:
+                raise ValueError(f"instance {i}: expected a float64 device vector of {self.n_global[i]}")
+            bp[i], xp[i] = b.data_ptr(), x.data_ptr()
+        opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
+                                  max_outer=max_outer, check_every=check_every)
+        st = (SolveStats * self.n)()
+        status = _lib.sem_batch_solve(self._h, ctypes.cast(bp, _p), ctypes.cast(xp, _p), ctypes.byref(opts),
+                                      ctypes.cast(st, _p), _stream(stream))
+        infos = [dict(iterations=s.iterations, outer=s.outer_iterations, rel_residual=s.rel_residual,
+                      solve_ms=s.solve_ms) for s in st]
+        if status != SEM_OK and (status != SEM_ENOCONV or raise_on_noconv):
+            raise SemError(status, last_error())
+        return xs, infos, status
 
 
 def library_symbols():

@@ -185,3 +185,39 @@ def test_custom_dirichlet_set():
     ut, _, _, _ = P.solve(b, rtol=1e-13)
     xg, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
     assert rel_l2(xg.cpu().numpy(), ut) <= 1e-10
+
+
+def test_autotuned_tile_gives_identical_results():
+    """The tile only regroups elements into workgroups: results are bitwise
+    equal to the default tile's, and the tuned tile is one of the candidates."""
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(4, perturb=0.1)
+    m, _ = meshgen.permute_elements(m, seed=61)
+    for N in (3, 4, 7):
+        Ma = sem.Mesh(m.vtx, m.hex, N, autotune=False)
+        Mb = sem.Mesh(m.vtx, m.hex, N, autotune=True)
+        assert Mb.tile(sem.SEM_F64) in (1, 2, 4, 8) and Mb.tile(sem.SEM_F32) in (1, 2, 4, 8)
+        u = torch.tensor(np.random.default_rng(62).uniform(-1, 1, Ma.n_global), device=dev)
+        assert torch.equal(Ma.apply_A(u), Mb.apply_A(u))
+        u32 = u.float()
+        assert torch.equal(Ma.apply_A(u32), Mb.apply_A(u32))
+
+
+@pytest.mark.parametrize("tile", [1, 16])
+def test_order15_operator_variants(tile):
+    """N = 15: the vector kernel and the FP64 matrix-core kernel both match the
+    oracle (two elements, one face shared, ragged permuted numbering)."""
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh((2, 1, 2), perturb=0.1, seed=71)
+    m, _ = meshgen.rotate_elements(m, seed=72)
+    m, _ = meshgen.permute_elements(m, seed=73)
+    M = sem.Mesh(m.vtx, m.hex, 15, autotune=False)
+    M.set_tile(tile)
+    P = Problem(m.vtx, m.hex, 15, fine=False, coarse=False)
+    u = np.random.default_rng(74).uniform(-1, 1, M.n_global)
+    y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
+    assert rel_l2(y, P.A(u)) <= 1e-12
+    with pytest.raises(sem.SemError):
+        M.set_tile(16, sem.SEM_F32)
