@@ -79,6 +79,8 @@ struct sem_mesh_s {
   hipGraphExec_t coarse_graph = nullptr;  // the level sweeps, captured once per factorisation
   bool direct_coarse = false;             // launch the sweeps directly (inside an enclosing capture)
   int epb[2] = {0, 0};                    // operator tile (elements per workgroup) for FP64, FP32
+  hipStream_t side_stream = nullptr;      // coarse chain of the preconditioner, beside the patch solves
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t capture_stream = nullptr;
   // PCG work
   DBuf<double> v64[5];

@@ -276,12 +276,31 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     SEM_HIP(hipGetLastError());
     return;
   }
-  fdm_and_restrict<T>(m, r, fine, coarse, s);
+  // The coarse and fine parts are independent until the final sum: the
+  // coarse chain (restriction, level sweeps) runs on a second stream while the
+  // patch solves run on the caller's stream; both join before the gather.
+  hipStream_t sc = s;
+  if (coarse && fine) {
+    if (!m->side_stream) {
+      SEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
+      SEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+      SEM_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
+    }
+    SEM_HIP(hipEventRecord(m->ev_fork, s));
+    SEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
+    sc = m->side_stream;
+  }
   if (coarse) {
-    hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, s, m->Rlev.p, m->Re.p,
+    fdm_and_restrict<T>(m, r, false, true, sc);
+    hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, sc, m->Rlev.p, m->Re.p,
                        m->vinc_off.p, m->vinc_ec.p, m->cidx.p, H.V);
     SEM_HIP(hipGetLastError());
-    coarse_solve_levels(m, s);
+    coarse_solve_levels(m, sc);
+  }
+  if (fine) fdm_and_restrict<T>(m, r, true, false, s);
+  if (sc != s) {
+    SEM_HIP(hipEventRecord(m->ev_join, sc));
+    SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
   }
   hipLaunchKernelGGL((precond_gather_kernel<T>), dim3((unsigned)blocks_for(H.n_global)), dim3(kGS), 0, s, z,
                      (const T*)ZPp<T>(m), m->ip_off.p, m->ip_slot.p, m->dir.p, H.n_global, (int)fine,
@@ -819,6 +838,9 @@ int sem_mesh_destroy(sem_mesh m) {
     (void)hipDeviceSynchronize();
     release_coarse_graph(m);
     if (m->capture_stream) (void)hipStreamDestroy(m->capture_stream);
+    if (m->side_stream) (void)hipStreamDestroy(m->side_stream);
+    if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
+    if (m->ev_join) (void)hipEventDestroy(m->ev_join);
   }
   delete m;
   return SEM_OK;

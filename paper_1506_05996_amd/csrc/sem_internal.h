@@ -29,7 +29,7 @@ void set_error(const std::string& msg);
 //     wid = wbase + ai*i + aj*j + ak*k.
 // Record layout (int32 x4): gbase, packed coefficients (three signed 10-bit
 // fields), wbase, flags.
-constexpr int kRecInts = 4;
+constexpr int kRecInts = 4;  // kernels read a record as one int4
 constexpr int kClasses = 27;
 constexpr int kInteriorClass = 13;
 constexpr int kFlagOwned = 1;     // this element holds the first local copy of the node

@@ -82,17 +82,31 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   const bool valid = pos < E;
   const int64_t e = valid ? order[pos] : 0;
   const int cx = node_class(i, N), cy = node_class(j, N);
-  for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
-  T rw[n1];
-#pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
-    sU[le][k * P + ij] = valid ? u[a.g] : T(0);
-    rw[k] = T(0);
-  }
+  // The lane's k-pencil crosses three entity records (k = 0, interior k,
+  // k = N).  Loads go out in dependency order with no wait between them:
+  // records, then the factors of plane 0, then all u values, then D.
+  const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+  const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
   // factors of plane k in registers, plane k+1 prefetched during plane k
   const T* Ge = G + e * 6 * NN + ij;
   T g0 = Ge[0 * NN], g1 = Ge[1 * NN], g2 = Ge[2 * NN], g3 = Ge[3 * NN], g4 = Ge[4 * NN], g5 = Ge[5 * NN];
+  T rw[n1];
+  {
+    T uv[n1];
+#pragma unroll
+    for (int k = 0; k < n1; ++k) {
+      const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+      int ai, aj, ak;
+      unpack_coef(r.y, ai, aj, ak);
+      uv[k] = u[r.x + ai * i + aj * j + ak * k];
+    }
+    for (int x = tid; x < P; x += EPB * P) sD[x] = Dg[x];
+#pragma unroll
+    for (int k = 0; k < n1; ++k) {
+      sU[le][k * P + ij] = valid ? uv[k] : T(0);
+      rw[k] = T(0);
+    }
+  }
   __syncthreads();
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
@@ -132,11 +146,14 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
-    const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
-    if (a.flags & kFlagInterior)
-      y[a.g] = (masked_interior && dir[a.g]) ? T(0) : rw[k];
+    const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+    int ai, aj, ak;
+    unpack_coef(r.y, ai, aj, ak);
+    const int off = ai * i + aj * j + ak * k;
+    if (r.w & kFlagInterior)
+      y[r.x + off] = (masked_interior && dir[r.x + off]) ? T(0) : rw[k];
     else
-      w[a.w] = rw[k];
+      w[r.z + off] = rw[k];
   }
 }
 
@@ -144,7 +161,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
 // Operator at N = 15 on FP64 matrix cores (v_mfma_f64_16x16x4f64).  One
 // workgroup of four waves per element (16^3 nodes).  MFMA operand layout for
 // a 16x16 product with K = 4: lane l supplies A[l%16][l/16] and B[l/16][l%16]
-// and receives D[4(l/16)+r][l%16], r = 0..3.
+// and receives D[4r + l/16][l%16] in accumulator register r = 0..3.
 //   1. zeta derivative  UT = D (16x16) x U (16 x 256 columns (j,i)), 4 tiles per wave
 //   2. per plane k (4 planes per wave): UR = U_k D^T, US = D U_k, the factors
 //      G at the lane's 4 nodes, A, B, C; then W_k = A_k D + D^T B_k
@@ -170,11 +187,18 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
   {
     const int i0 = tid & 15, j0 = tid >> 4;
     const int cx = node_class(i0, N), cy = node_class(j0, N);
-#pragma unroll 4
+    const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+    const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
+    double uv[n1];
+#pragma unroll
     for (int k = 0; k < n1; ++k) {
-      const NodeAddr a = node_addr(rec, e, cx, cy, k, i0, j0, N);
-      sU[k * P + tid] = u[a.g];
+      const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+      int ai, aj, ak;
+      unpack_coef(r.y, ai, aj, ak);
+      uv[k] = u[r.x + ai * i0 + aj * j0 + ak * k];
     }
+#pragma unroll
+    for (int k = 0; k < n1; ++k) sU[k * P + tid] = uv[k];
   }
   double DA[4], DB[4];  // DA[s] = D[lr][4s+lq] (A layout of D), DB[s] = D[4s+lq][lr] (B layout)
 #pragma unroll
@@ -191,7 +215,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
     for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(DA[s], sU[(4 * s + lq) * P + t * 16 + lr], acc, 0, 0, 0);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sT[(4 * lq + r) * P + t * 16 + lr] = acc[r];
+    for (int r = 0; r < 4; ++r) sT[(4 * r + lq) * P + t * 16 + lr] = acc[r];
   }
   __syncthreads();
   // 2. planes
@@ -209,15 +233,15 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int node = k * P + (4 * lq + r) * n1 + lr;
+      const int node = k * P + (4 * r + lq) * n1 + lr;
       const double ut = sT[node];
       const double g0 = Ge[0 * NN + node], g1 = Ge[1 * NN + node], g2 = Ge[2 * NN + node];
       const double g3 = Ge[3 * NN + node], g4 = Ge[4 * NN + node], g5 = Ge[5 * NN + node];
       const double A = g0 * ur[r] + g1 * us[r] + g2 * ut;
       const double B = g1 * ur[r] + g3 * us[r] + g4 * ut;
       const double C = g2 * ur[r] + g4 * us[r] + g5 * ut;
-      sS[wave][0][(4 * lq + r) * n1 + lr] = A;
-      sS[wave][1][(4 * lq + r) * n1 + lr] = B;
+      sS[wave][0][(4 * r + lq) * n1 + lr] = A;
+      sS[wave][1][(4 * r + lq) * n1 + lr] = B;
       sT[node] = C;  // plane k of the zeta derivative is no longer needed
     }
     __syncthreads();
@@ -234,7 +258,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sU[(wave * 4 + q) * P + (4 * lq + r) * n1 + lr] = W[q][r];
+    for (int r = 0; r < 4; ++r) sU[(wave * 4 + q) * P + (4 * r + lq) * n1 + lr] = W[q][r];
   __syncthreads();
   // 3. zeta transpose and output: tile t = row j of every plane
   const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
@@ -247,7 +271,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
     const int j = t, i = lr, cx = node_class(i, N), cy = node_class(j, N);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int k = 4 * lq + r;
+      const int k = 4 * r + lq;
       const double v = acc[r] + sU[k * P + j * n1 + i];
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
       if (a.flags & kFlagInterior)
