@@ -332,9 +332,18 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restric
   if (pos >= E) return;
   const int64_t e = order[pos];
   const int32_t* ipe = ip + e * MMM;
-  for (int x = tid; x < MMM; x += NT) {
-    const int32_t g = ipe[x];
-    X[x] = g >= 0 ? r[g] : T(0);
+  {
+    // all index loads, then all residual loads, then the LDS stores
+    constexpr int R = (MMM + NT - 1) / NT;
+    int32_t gi[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) gi[q] = (tid + q * NT < MMM) ? ipe[tid + q * NT] : -1;
+    T rv[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) rv[q] = r[gi[q] >= 0 ? gi[q] : 0];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+      if (tid + q * NT < MMM) X[tid + q * NT] = gi[q] >= 0 ? rv[q] : T(0);
   }
   __syncthreads();
   const T hx = hg[e * 3 + 0], hy = hg[e * 3 + 1], hz = hg[e * 3 + 2];
@@ -438,21 +447,49 @@ precond_gather_kernel(T* __restrict__ z, const T* __restrict__ zP, const int32_t
                       const int32_t* __restrict__ rec, const double* __restrict__ phi, int N) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ng) return;
+  // Loads go out chain by chain with no wait inside a level: slot range and
+  // owner, then up to kPre slots and the 8 vertex records, then the patch
+  // values and coarse values.
+  constexpr int kPre = 8;
   T s = 0;
-  if (use_fine)
-    for (int32_t q = ip_off[g]; q < ip_off[g + 1]; ++q) s += zP[ip_slot[q]];
+  int32_t q0 = 0, q1 = 0;
+  if (use_fine) {
+    q0 = ip_off[g];
+    q1 = ip_off[g + 1];
+  }
+  int32_t o = 0;
+  if (Zv != nullptr) o = owner[g];
+  int32_t sl[kPre];
+#pragma unroll
+  for (int t = 0; t < kPre; ++t) sl[t] = (q0 + t < q1) ? ip_slot[q0 + t] : -1;
+  const int n1 = N + 1, nn = n1 * n1 * n1;
+  const int64_t e = o / nn;
+  int32_t vid[8];
   if (Zv != nullptr) {
-    const int n1 = N + 1, nn = n1 * n1 * n1;
-    const int32_t o = owner[g];
-    const int64_t e = o / nn;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cls = 2 * (c & 1) + 6 * ((c >> 1) & 1) + 18 * (c >> 2);
+      vid[c] = rec[(e * kClasses + cls) * kRecInts];
+    }
+  }
+  T pv[kPre];
+#pragma unroll
+  for (int t = 0; t < kPre; ++t) pv[t] = zP[sl[t] >= 0 ? sl[t] : 0];
+#pragma unroll
+  for (int t = 0; t < kPre; ++t)
+    if (sl[t] >= 0) s += pv[t];
+  for (int32_t q = q0 + kPre; q < q1; ++q) s += zP[ip_slot[q]];
+  if (Zv != nullptr) {
+    double zc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) zc[c] = Zv[vid[c]];
     const int loc = o - (int)e * nn;
     const int i = loc % n1, j = (loc / n1) % n1, k = loc / (n1 * n1);
     double acc = 0.0;
+#pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int I = c & 1, J = (c >> 1) & 1, K = c >> 2;
-      const int cls = 2 * I + 3 * (2 * J) + 9 * (2 * K);
-      const int32_t v = rec[(e * kClasses + cls) * kRecInts];
-      acc += phi[I * n1 + i] * phi[J * n1 + j] * phi[K * n1 + k] * Zv[v];
+      acc += phi[I * n1 + i] * phi[J * n1 + j] * phi[K * n1 + k] * zc[c];
     }
     s += (T)acc;
   }
@@ -473,17 +510,25 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
   if (pos >= E) return;
   const int64_t e = order[pos];
   const int cx = node_class(i, N), cy = node_class(j, N);
+  // the three records of the lane's k-pencil, then all its residual values
+  const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+  const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
+  T rv[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
+    int ai, aj, ak;
+    unpack_coef(rr.y, ai, aj, ak);
+    rv[k] = r[rr.x + ai * i + aj * j + ak * k];
+  }
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
-    const int cz = node_class(k, N);
-    const int32_t* rr = rec + ((e * kClasses + cx + 3 * cy + 9 * cz) * kRecInts);
-    if (rr[3] & kFlagOwned) {
-      int ai, aj, ak;
-      unpack_coef(rr[1], ai, aj, ak);
-      const double v = (double)r[rr[0] + ai * i + aj * j + ak * k];
+    const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
+    if (rr.w & kFlagOwned) {
+      const double v = (double)rv[k];
 #pragma unroll
       for (int c = 0; c < 8; ++c)
         acc[c] += phi[(c & 1) * n1 + i] * phi[((c >> 1) & 1) * n1 + j] * phi[(c >> 2) * n1 + k] * v;
@@ -493,9 +538,17 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
   for (int c = 0; c < 8; ++c) red[c][tid] = acc[c];
   __syncthreads();
   if (tid < 8) {
-    double s = 0.0;
-    for (int x = 0; x < P; ++x) s += red[tid][x];
-    Re[e * 8 + tid] = s;
+    // four interleaved partial sums, combined in a fixed order
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int x = 0;
+    for (; x + 3 < P; x += 4) {
+      s0 += red[tid][x];
+      s1 += red[tid][x + 1];
+      s2 += red[tid][x + 2];
+      s3 += red[tid][x + 3];
+    }
+    for (; x < P; ++x) s0 += red[tid][x];
+    Re[e * 8 + tid] = (s0 + s1) + (s2 + s3);
   }
 }
 
