@@ -71,12 +71,14 @@ struct sem_mesh_s {
   DBuf<int32_t> ip, ip_off, ip_slot;
   DBuf<double> S64, lam64, h64, zP64;
   DBuf<float> S32, lam32, h32, zP32;
-  // coarse
-  DBuf<double> phi, Re, Rlev, Wlev, Xlev, Ylev, Zv, sinv, ac_val;
-  DBuf<int32_t> ac_off, ac_col, lo_off, lo_col, up_off, up_col, row_blk;
-  DBuf<Block> blocks;
-  DBuf<double> lo_val, up_val;
-  hipGraphExec_t coarse_graph = nullptr;  // the level sweeps, captured once per factorisation
+  // coarse: vectors in coarse order (R, y, Z, X), vertex-order solution Zv,
+  // the nested-dissection fronts and their work lists
+  DBuf<double> phi, Re, Rlev, Ylev, Wlev, Xlev, Zv;
+  DBuf<double> fwd_pool, bwd_pool, cvec;
+  DBuf<FrontNode> fnodes;
+  DBuf<int32_t> fb_idx, ct_off, ct_pos, fy_items;
+  DBuf<RowItem> fr_items, br_items;
+  hipGraphExec_t coarse_graph = nullptr;  // the solve sweeps, captured once per factorisation
   bool direct_coarse = false;             // launch the sweeps directly (inside an enclosing capture)
   int epb[2] = {0, 0};                    // operator tile (elements per workgroup) for FP64, FP32
   hipStream_t side_stream = nullptr;      // coarse chain of the preconditioner, beside the patch solves

@@ -196,37 +196,25 @@ void fdm_and_restrict(sem_mesh m, const T* r, bool fine, bool coarse, hipStream_
   }
 }
 
-size_t max_block(const HostTables& T) {
-  size_t mx = 0;
-  for (auto& B : T.blocks) mx = std::max<size_t>(mx, B.size);
-  return mx;
-}
-
-
-
-// Rlev (level order) -> Zv (vertex order): block LDL^T sweeps
+// Rlev (coarse order) -> Zv (vertex order): nested-dissection sweeps
 void coarse_sweeps(sem_mesh m, hipStream_t s) {
   const HostTables& T = m->T;
-  const int nl = (int)T.levels.size();
-  for (int k = 0; k < nl; ++k) {
-    const Level& L = T.levels[k];
-    hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
-                       m->Rlev.p, m->Wlev.p, m->lo_off.p, m->lo_col.p, m->lo_val.p, L.off, L.size, 1);
-    hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Wlev.p, m->Wlev.p, m->Ylev.p,
-                       m->sinv.p, m->blocks.p, m->row_blk.p, L.off, L.size, 0);
+  const int H = T.n_heights;
+  for (int h = 0; h < H; ++h) {
+    const int64_t ny = T.fy_off[h + 1] - T.fy_off[h], nr = T.fr_off[h + 1] - T.fr_off[h];
+    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)blocks_for(ny)), dim3(kGS), 0, s, m->Ylev.p,
+                       (const double*)m->Rlev.p, (const double*)m->cvec.p, m->ct_off.p, m->ct_pos.p,
+                       m->fy_items.p + T.fy_off[h], ny);
+    hipLaunchKernelGGL(coarse_fwd_kernel, dim3((unsigned)((nr + 3) / 4)), dim3(256), 0, s, m->Wlev.p, m->cvec.p,
+                       (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
+                       m->fr_items.p + T.fr_off[h], nr);
     SEM_HIP(hipGetLastError());
   }
-  for (int k = nl - 1; k >= 0; --k) {
-    const Level& L = T.levels[k];
-    if (k == nl - 1) {
-      hipLaunchKernelGGL((copy_kernel<double, double>), dim3(grid_stride_blocks(L.size)), dim3(kGS), 0, s,
-                         m->Xlev.p + L.off, (const double*)m->Wlev.p + L.off, L.size);
-    } else {
-      hipLaunchKernelGGL(coarse_couple_kernel, dim3((unsigned)blocks_for(8 * L.size)), dim3(kGS), 0, s, m->Ylev.p,
-                         m->Rlev.p, m->Xlev.p, m->up_off.p, m->up_col.p, m->up_val.p, L.off, L.size, 0);
-      hipLaunchKernelGGL(coarse_gemv_kernel, dim3((unsigned)L.size), dim3(256), 0, s, m->Xlev.p, m->Wlev.p,
-                         m->Ylev.p, m->sinv.p, m->blocks.p, m->row_blk.p, L.off, L.size, 1);
-    }
+  for (int h = H - 1; h >= 0; --h) {
+    const int64_t nb = T.br_off[h + 1] - T.br_off[h];
+    hipLaunchKernelGGL(coarse_bwd_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, m->Xlev.p,
+                       (const double*)m->Wlev.p, (const double*)m->bwd_pool.p, m->fb_idx.p, m->fnodes.p,
+                       m->br_items.p + T.br_off[h], nb);
     SEM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,
@@ -308,91 +296,131 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
   SEM_HIP(hipGetLastError());
 }
 
-// --- coarse factorisation (set-up): per block b of level k, the Schur
-// complement S_b = A_bb - A_{b,p} Sinv_p A_{p,b} (p: the component's block in
-// level k-1) and its dense inverse Sinv_b
+// --- coarse factorisation (set-up), multifrontal in post-order.  Node t's
+// front F (f = s + b, column-major) holds the entries of A_c with the smaller
+// index in t's own range, plus the update matrices of its children
+// (extend-add).  Then S = F_II, S^-1 by Cholesky, W^T = S^-1 F_IB,
+// W = F_BI S^-1 and the update U = F_BB - W F_IB for the parent.
 void factor_coarse(sem_mesh m) {
   HostTables& T = m->T;
   release_coarse_graph(m);
-  m->ac_off.upload(T.ac_off.data(), T.ac_off.size());
-  m->ac_col.upload(T.ac_col.data(), T.ac_col.size());
-  m->ac_val.upload(T.ac_val.data(), T.ac_val.size());
-  m->lo_off.upload(T.lo_off.data(), T.lo_off.size());
-  m->lo_col.upload(T.lo_col.data(), T.lo_col.size());
-  m->lo_val.upload(T.lo_val.data(), T.lo_val.size());
-  m->up_off.upload(T.up_off.data(), T.up_off.size());
-  m->up_col.upload(T.up_col.data(), T.up_col.size());
-  m->up_val.upload(T.up_val.data(), T.up_val.size());
   m->cidx.upload(T.cidx.data(), T.cidx.size());
-  m->row_blk.upload(T.row_blk.data(), T.row_blk.size());
-  m->blocks.upload(T.blocks.data(), T.blocks.size());
   const size_t nc = std::max<int64_t>(T.nc, 1);
   m->Rlev.alloc(nc);
+  m->Ylev.alloc(nc);
   m->Wlev.alloc(nc);
   m->Xlev.alloc(nc);
-  m->Ylev.alloc(nc);
   if (T.nc == 0) {
-    m->sinv.release();
+    m->fwd_pool.release();
+    m->bwd_pool.release();
     return;
   }
-  // dense inverse Schur complements are kept per block: bound their size
-  if (max_block(T) > 16384)
-    throw Error{SEM_EUNSUPPORTED, "coarse block of " + std::to_string(max_block(T)) + " vertices exceeds 16384"};
-  m->sinv.alloc(T.sinv_size);
+  // fronts are factored densely: bound their size
+  if (T.max_front > 16384)
+    throw Error{SEM_EUNSUPPORTED, "coarse front of " + std::to_string(T.max_front) + " vertices exceeds 16384"};
+  m->fnodes.upload(T.fnodes.data(), T.fnodes.size());
+  m->fb_idx.upload(T.fb_idx.data(), T.fb_idx.size());
+  m->ct_off.upload(T.ct_off.data(), T.ct_off.size());
+  m->ct_pos.upload(T.ct_pos.data(), T.ct_pos.size());
+  m->fy_items.upload(T.fy_items.data(), T.fy_items.size());
+  m->fr_items.upload(T.fr_items.data(), T.fr_items.size());
+  m->br_items.upload(T.br_items.data(), T.br_items.size());
+  m->cvec.alloc(std::max<int64_t>(T.c_size, 1));
+  m->fwd_pool.alloc(T.fwd_size);
+  m->bwd_pool.alloc(std::max<int64_t>(T.bwd_size, 1));
   rocblas_handle hb;
   if (rocblas_create_handle(&hb) != rocblas_status_success) throw Error{SEM_EHIP, "rocblas_create_handle failed"};
   std::unique_ptr<std::remove_pointer<rocblas_handle>::type, decltype(&rocblas_destroy_handle)> guard(
       hb, rocblas_destroy_handle);
-  DBuf<double> Bd, Td;
+  const int64_t mf = T.max_front;
+  DBuf<double> Fd, Ust;
+  DBuf<int32_t> mapd;
   DBuf<rocblas_int> info;
   info.alloc(1);
-  const size_t mx = max_block(T);
-  Bd.alloc(mx * mx);
-  Td.alloc(mx * mx);
-  std::vector<double> dense;
-  for (size_t b = 0; b < T.blocks.size(); ++b) {
-    const Block& L = T.blocks[b];
-    // A_bb, column-major (symmetric)
-    dense.assign(L.size * L.size, 0.0);
-    for (int64_t r = 0; r < L.size; ++r)
-      for (int32_t q = T.ac_off[L.off + r]; q < T.ac_off[L.off + r + 1]; ++q) {
-        const int64_t c = T.ac_col[q] - L.off;
-        if (c >= 0 && c < L.size) dense[r + c * L.size] = T.ac_val[q];
+  Fd.alloc((size_t)mf * mf);
+  Ust.alloc(std::max<int64_t>(T.ustack_size, 1));
+  mapd.alloc((size_t)mf);
+  std::vector<double> cols;
+  std::vector<int32_t> map;
+  std::vector<int64_t> u_at(T.fnodes.size(), -1);  // update matrix position in the stack
+  int64_t top = 0;
+  const double one = 1.0, zero = 0.0, mone = -1.0;
+  for (size_t q = 0; q < T.fnodes.size(); ++q) {
+    const FrontNode& F = T.fnodes[q];
+    const int64_t s = F.s, b = F.b, f = s + b, end = F.off + s;
+    const int32_t* B = T.fb_idx.data() + F.bidx;
+    auto local = [&](int64_t g) -> int64_t {
+      if (g >= F.off && g < end) return g - F.off;
+      const int32_t* p = std::lower_bound(B, B + b, (int32_t)g);
+      if (p == B + b || *p != g) throw Error{SEM_EMESH, "coarse front: entry outside the node's front"};
+      return s + (p - B);
+    };
+    // columns of the own vertices: A_c(idx, own) (entries towards eliminated
+    // vertices were taken by the descendants' fronts)
+    cols.assign((size_t)f * s, 0.0);
+    for (int64_t r = 0; r < s; ++r)
+      for (int32_t k = T.ac_off[F.off + r]; k < T.ac_off[F.off + r + 1]; ++k) {
+        if (T.ac_col[k] < F.off) continue;
+        cols[(size_t)r * f + local(T.ac_col[k])] = T.ac_val[k];
       }
-    double* Sk = m->sinv.p + L.sinv;
-    SEM_HIP(hipMemcpy(Sk, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
-    if (L.prev >= 0) {
-      const Block& P = T.blocks[L.prev];
-      // B = A_{p,b}: rows of block p, columns of block b (column-major, ld = |p|)
-      dense.assign(P.size * L.size, 0.0);
-      for (int64_t r = 0; r < P.size; ++r)
-        for (int32_t q = T.ac_off[P.off + r]; q < T.ac_off[P.off + r + 1]; ++q) {
-          const int64_t c = T.ac_col[q] - L.off;
-          if (c >= 0 && c < L.size) dense[r + c * P.size] = T.ac_val[q];
-        }
-      SEM_HIP(hipMemcpy(Bd.p, dense.data(), dense.size() * sizeof(double), hipMemcpyHostToDevice));
-      const double one = 1.0, zero = 0.0, mone = -1.0;
-      const rocblas_int pn = (rocblas_int)P.size, ln = (rocblas_int)L.size;
-      // T = Sinv_p B
-      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, pn, ln, pn, &one,
-                        m->sinv.p + P.sinv, pn, Bd.p, pn, &zero, Td.p, pn) != rocblas_status_success)
-        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
-      // S_b = A_bb - B^T T
-      if (rocblas_dgemm(hb, rocblas_operation_transpose, rocblas_operation_none, ln, ln, pn, &mone, Bd.p, pn, Td.p,
-                        pn, &one, Sk, ln) != rocblas_status_success)
-        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+    SEM_HIP(hipMemcpy(Fd.p, cols.data(), cols.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (b > 0) {
+      SEM_HIP(hipMemset(Fd.p + s * f, 0, (size_t)b * f * sizeof(double)));
+      hipLaunchKernelGGL(front_transpose_kernel, dim3((unsigned)blocks_for(s * b)), dim3(kGS), 0, 0, Fd.p, f, s, b);
+      SEM_HIP(hipGetLastError());
     }
-    if (rocsolver_dpotrf(hb, rocblas_fill_lower, (rocblas_int)L.size, Sk, (rocblas_int)L.size, info.p) !=
+    // extend-add the children's update matrices, then pop them
+    int64_t first = -1;
+    for (int32_t c : T.fchildren[q]) {
+      const FrontNode& C = T.fnodes[c];
+      if (C.b == 0) continue;
+      map.resize(C.b);
+      for (int32_t k = 0; k < C.b; ++k) map[k] = (int32_t)local(T.fb_idx[C.bidx + k]);
+      SEM_HIP(hipMemcpy(mapd.p, map.data(), map.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(front_extend_add_kernel, dim3((unsigned)blocks_for((int64_t)C.b * C.b)), dim3(kGS), 0, 0,
+                         Fd.p, f, (const double*)Ust.p + u_at[c], (int64_t)C.b, (const int32_t*)mapd.p);
+      SEM_HIP(hipGetLastError());
+      if (first < 0 || u_at[c] < first) first = u_at[c];
+    }
+    if (first >= 0) top = first;
+    // S^-1 in place (lower triangle), mirrored
+    if (rocsolver_dpotrf(hb, rocblas_fill_lower, (rocblas_int)s, Fd.p, (rocblas_int)f, info.p) !=
         rocblas_status_success)
       throw Error{SEM_EHIP, "rocsolver_dpotrf failed"};
     rocblas_int ih = 0;
     SEM_HIP(hipMemcpy(&ih, info.p, sizeof(ih), hipMemcpyDeviceToHost));
     if (ih != 0) throw Error{SEM_EMESH, "coarse matrix is not positive definite"};
-    if (rocsolver_dpotri(hb, rocblas_fill_lower, (rocblas_int)L.size, Sk, (rocblas_int)L.size, info.p) !=
+    if (rocsolver_dpotri(hb, rocblas_fill_lower, (rocblas_int)s, Fd.p, (rocblas_int)f, info.p) !=
         rocblas_status_success)
       throw Error{SEM_EHIP, "rocsolver_dpotri failed"};
-    hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)blocks_for(L.size * L.size)), dim3(kGS), 0, 0, Sk, L.size);
+    hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)blocks_for(s * s)), dim3(kGS), 0, 0, Fd.p, s, f);
     SEM_HIP(hipGetLastError());
+    // forward matrix [S^-1 ; W] row-major = column-major s x (s + b): [S^-1 | W^T]
+    double* X = m->fwd_pool.p + F.fwd;
+    SEM_HIP(hipMemcpy2D(X, s * sizeof(double), Fd.p, f * sizeof(double), s * sizeof(double), s,
+                        hipMemcpyDeviceToDevice));
+    if (b > 0) {
+      const rocblas_int si = (rocblas_int)s, bi = (rocblas_int)b, fi = (rocblas_int)f;
+      // W^T = S^-1 F_IB  (s x b)
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, si, bi, si, &one, Fd.p, fi,
+                        Fd.p + s * f, fi, &zero, X + s * s, si) != rocblas_status_success)
+        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      // W = F_BI S^-1  (b x b... b x s, column-major = row-major W^T for the backward sweep)
+      double* Wb = m->bwd_pool.p + F.bwd;
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, bi, si, si, &one, Fd.p + s, fi, Fd.p,
+                        fi, &zero, Wb, bi) != rocblas_status_success)
+        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      // U = F_BB - W F_IB, pushed for the parent
+      if (top + b * b > std::max<int64_t>(T.ustack_size, 1)) throw Error{SEM_EHIP, "coarse update stack overflow"};
+      double* U = Ust.p + top;
+      SEM_HIP(hipMemcpy2D(U, b * sizeof(double), Fd.p + s + s * f, f * sizeof(double), b * sizeof(double), b,
+                          hipMemcpyDeviceToDevice));
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, bi, bi, si, &mone, Wb, bi, Fd.p + s * f,
+                        fi, &one, U, bi) != rocblas_status_success)
+        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      u_at[q] = top;
+      top += b * b;
+    }
   }
   SEM_HIP(hipDeviceSynchronize());
 }
@@ -768,7 +796,7 @@ sem_mesh_s* create_mesh(const double* vtx, int64_t n_vtx, const int64_t* hex, in
   build_geometry(T, vtx, hex);
   build_patches(T, hex);
   build_coarse_matrices(T, vtx, hex);
-  build_coarse_levels(T);
+  build_coarse_tree(T);
   m->epb[0] = m->epb[1] = default_tile(order);
   if (!m->host_only) {
     upload_all(m.get());
@@ -921,7 +949,7 @@ int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask) {
     HostTables& T = m->T;
     for (int64_t g = 0; g < T.n_global; ++g) T.dir[g] = mask[g] ? 1 : 0;
     // the coarse free set follows the vertex nodes: new levels, new factor
-    build_coarse_levels(T);
+    build_coarse_tree(T);
     update_interior_mask_flags(T);
     if (!m->host_only) {
       SEM_HIP(hipSetDevice(m->device));

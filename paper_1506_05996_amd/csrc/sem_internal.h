@@ -40,23 +40,30 @@ inline int32_t pack_coef(int ai, int aj, int ak) {
   return (ai & 0x3FF) | ((aj & 0x3FF) << 10) | ((ak & 0x3FF) << 20);
 }
 
-// Coarse levels: BFS levels of each connected component of the free-vertex
-// graph, merged by level index.  Level l is one contiguous range of coarse
-// indices made of one block per component; a block couples only to the block
-// of the same component in the neighbouring levels.
-struct Level {
-  int64_t off;         // first coarse index of the level
-  int64_t size;        // number of free vertices in the level
-  int32_t blk_begin;   // its blocks [blk_begin, blk_end)
-  int32_t blk_end;
+// Coarse solve by nested dissection.  The free-vertex graph of each connected
+// component is split recursively by separators (one BFS level across the
+// longest extent); the separators and the final small parts are the nodes of
+// a forest, numbered in post-order, and each node's own vertices form one
+// contiguous range of coarse indices.  A node t holds its own vertices I and
+// the boundary B: the vertices of its ancestors coupled to its subtree once
+// the subtree is eliminated.  After elimination of the subtree, the front
+// [F_II F_IB; F_BI F_BB] gives S = F_II and W = F_BI S^-1.
+struct FrontNode {
+  int64_t off;     // first coarse index of the node's own vertices
+  int64_t fwd;     // offset of [S^-1 ; W] ((s + b) x s, row-major) in the forward pool
+  int64_t bwd;     // offset of W^T (s x b, row-major) in the backward pool
+  int64_t bidx;    // offset of the boundary list (ascending coarse indices) in fb_idx
+  int64_t coff;    // offset of the node's contribution W y in the contribution vector
+  int32_t s;       // own vertices
+  int32_t b;       // boundary vertices
+  int32_t parent;  // -1 for a root
+  int32_t height;  // 0 for a leaf, else 1 + the largest height of its children
 };
 
-struct Block {
-  int64_t off;   // first coarse index
-  int64_t size;  // rows
-  int64_t sinv;  // offset of its dense inverse Schur complement in the pool
-  int32_t prev;  // block of the same component in the previous level, or -1
-  int32_t pad;
+// one row of a per-height work list: (node, row or column of that node)
+struct RowItem {
+  int32_t node;
+  int32_t row;
 };
 
 struct HostTables {
@@ -91,17 +98,22 @@ struct HostTables {
   std::vector<double> h;     // [E][3]
   std::vector<int32_t> order;  // element traversal order: Morton order of the centroids
 
-  // coarse space (order-1 operator on the free vertices, level-ordered)
+  // coarse space (order-1 operator on the free vertices, nested-dissection order)
   std::vector<int32_t> cidx;             // [V] coarse index or -1 (Dirichlet vertex)
   int64_t nc = 0;                        // number of free vertices
-  std::vector<Level> levels;
-  std::vector<Block> blocks;
-  std::vector<int32_t> row_blk;          // [nc] block of each coarse row
-  int64_t sinv_size = 0;
-  std::vector<int32_t> ac_off, ac_col;   // CSR of A_c in level order
+  std::vector<int32_t> ac_off, ac_col;   // CSR of A_c in coarse order
   std::vector<double> ac_val;
-  std::vector<int32_t> lo_off, lo_col, up_off, up_col;  // couplings to the previous / next level
-  std::vector<double> lo_val, up_val;
+  std::vector<FrontNode> fnodes;         // post-order
+  std::vector<std::vector<int32_t>> fchildren;  // children of each node, ascending
+  std::vector<int32_t> fb_idx;           // boundary lists
+  std::vector<int32_t> ct_off, ct_pos;   // [nc + 1]: contribution slots subtracted from each row
+  int64_t fwd_size = 0, bwd_size = 0, c_size = 0;
+  int64_t ustack_size = 0;               // largest sum of pending update matrices (set-up)
+  int32_t max_front = 0;                 // largest s + b
+  int32_t n_heights = 0;
+  std::vector<int32_t> fy_off, fy_items;  // per height: coarse rows to assemble
+  std::vector<int64_t> fr_off, br_off;    // per height: ranges of fr_items / br_items
+  std::vector<RowItem> fr_items, br_items;  // forward rows (s + b per node), backward columns (s per node)
   std::vector<double> corner_K;          // [E][8][8] order-1 element matrices
 };
 
@@ -111,7 +123,7 @@ void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n
 void build_geometry(HostTables& T, const double* vtx, const int64_t* hex);
 void build_patches(HostTables& T, const int64_t* hex);
 void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex);
-void build_coarse_levels(HostTables& T);
+void build_coarse_tree(HostTables& T, int leaf_max = 0);
 void export_l2g(const HostTables& T, int32_t* l2g);
 void update_interior_mask_flags(HostTables& T);
 int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k);

@@ -565,63 +565,86 @@ restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, co
   R[c] = s;
 }
 
-// Block LDL^T solve of the level-ordered coarse matrix (levels couple only to
-// their neighbours).  Each level step is two launches: the sparse coupling
-// with the neighbouring level, then a dense product with the level's inverse
-// Schur complement.
-//   forward  level k: Y_k = R_k - A_{k,k-1} W_{k-1};   W_k = Sinv_k Y_k
-//   backward level k: Y_k = A_{k,k+1} X_{k+1};        X_k = W_k - Sinv_k Y_k
-// The coupling lists hold only the entries towards the neighbouring level
-// (lower for the forward sweep, upper for the backward one); 8 lanes per row.
+// Nested-dissection solve of the coarse system, node by node in height order.
+//   forward, height h (leaves first), node t with own rows I and boundary B:
+//     y_I = R_I - (contributions W_d y_d of the descendants d with I in B_d)
+//     Z_I = S_t^-1 y_I,   c_t = W_t y_I        (one stacked product [S^-1; W] y)
+//   backward, height h (roots first):
+//     X_I = Z_I - W_t^T X_B
+// All rows are independent within a height; sums run in a fixed order.
+
+// y_i = R_i - sum of the contributions listed for row i (ascending node)
 __global__ void __launch_bounds__(256)
-coarse_couple_kernel(double* __restrict__ Y, const double* __restrict__ R, const double* __restrict__ V,
-                     const int32_t* __restrict__ off, const int32_t* __restrict__ col,
-                     const double* __restrict__ val, int64_t loff, int64_t lsize, int forward) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = gid >> 3;
-  const int sub = (int)(gid & 7);
-  if (r >= lsize) return;  // whole 8-lane groups leave together
-  const int64_t row = loff + r;
-  double s = 0.0;
-  for (int32_t q = off[row] + sub; q < off[row + 1]; q += 8) s += val[q] * V[col[q]];
-  s += __shfl_xor(s, 4, 8);
-  s += __shfl_xor(s, 2, 8);
-  s += __shfl_xor(s, 1, 8);
-  if (sub == 0) Y[row] = forward ? R[row] - s : s;
+coarse_assemble_kernel(double* __restrict__ Y, const double* __restrict__ R, const double* __restrict__ cvec,
+                       const int32_t* __restrict__ ct_off, const int32_t* __restrict__ ct_pos,
+                       const int32_t* __restrict__ items, int64_t n) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int32_t i = items[x];
+  double s = R[i];
+  for (int32_t q = ct_off[i]; q < ct_off[i + 1]; ++q) s -= cvec[ct_pos[q]];
+  Y[i] = s;
 }
 
-// Out_r = (sub ? W_r - (S_b Y_b)_r : (S_b Y_b)_r) for the rows r of one level,
-// S_b the dense symmetric inverse Schur complement of the row's block: one
-// workgroup per row, its four waves take one quarter of the block's columns
-// each with eight independent partial sums per lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// one wave per row of the stacked matrix [S^-1; W] of a node (row-major,
+// s columns); rows < s give Z, the others the node's contribution
 __global__ void __launch_bounds__(256)
-coarse_gemv_kernel(double* __restrict__ Out, const double* __restrict__ W, const double* __restrict__ Y,
-                   const double* __restrict__ Spool, const Block* __restrict__ blocks,
-                   const int32_t* __restrict__ row_blk, int64_t loff, int64_t lsize, int sub) {
-  __shared__ double part[4];
-  if ((int64_t)blockIdx.x >= lsize) return;
-  const int64_t row = loff + blockIdx.x;
-  const Block B = blocks[row_blk[row]];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t n = B.size;
-  const int64_t q4 = (n + 3) / 4, c0 = wave * q4, c1 = c0 + q4 < n ? c0 + q4 : n;
-  const double* Sr = Spool + B.sinv + (row - B.off) * n;
-  const double* y = Y + B.off;
-  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  int64_t c = c0 + lane;
-  for (; c + 448 < c1; c += 512) {
-#pragma unroll
-    for (int q = 0; q < 8; ++q) a[q] += Sr[c + 64 * q] * y[c + 64 * q];
+coarse_fwd_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ Y,
+                  const double* __restrict__ pool, const FrontNode* __restrict__ nodes,
+                  const RowItem* __restrict__ items, int64_t n) {
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (it >= n) return;  // whole wave
+  const RowItem ri = items[it];
+  const FrontNode nd = nodes[ri.node];
+  const double* row = pool + nd.fwd + (int64_t)ri.row * nd.s;
+  const double* y = Y + nd.off;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int c = lane;
+  for (; c + 192 < nd.s; c += 256) {
+    a0 += row[c] * y[c];
+    a1 += row[c + 64] * y[c + 64];
+    a2 += row[c + 128] * y[c + 128];
+    a3 += row[c + 192] * y[c + 192];
   }
-  for (; c < c1; c += 64) a[0] += Sr[c] * y[c];
-  double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-  if (lane == 0) part[wave] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double t = (part[0] + part[1]) + (part[2] + part[3]);
-    Out[row] = sub ? W[row] - t : t;
+  for (; c < nd.s; c += 64) a0 += row[c] * y[c];
+  const double v = wave_sum((a0 + a1) + (a2 + a3));
+  if (lane == 0) {
+    if (ri.row < nd.s)
+      Z[nd.off + ri.row] = v;
+    else
+      cvec[nd.coff + ri.row - nd.s] = v;
   }
+}
+
+// one wave per own column c of a node: X_c = Z_c - (W^T)_c . X_B
+__global__ void __launch_bounds__(256)
+coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const double* __restrict__ pool,
+                  const int32_t* __restrict__ fb_idx, const FrontNode* __restrict__ nodes,
+                  const RowItem* __restrict__ items, int64_t n) {
+  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (it >= n) return;  // whole wave
+  const RowItem ri = items[it];
+  const FrontNode nd = nodes[ri.node];
+  const double* row = pool + nd.bwd + (int64_t)ri.row * nd.b;
+  const int32_t* bi = fb_idx + nd.bidx;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = lane;
+  for (; k + 192 < nd.b; k += 256) {
+    a0 += row[k] * X[bi[k]];
+    a1 += row[k + 64] * X[bi[k + 64]];
+    a2 += row[k + 128] * X[bi[k + 128]];
+    a3 += row[k + 192] * X[bi[k + 192]];
+  }
+  for (; k < nd.b; k += 64) a0 += row[k] * X[bi[k]];
+  const double v = wave_sum((a0 + a1) + (a2 + a3));
+  if (lane == 0) X[nd.off + ri.row] = Z[nd.off + ri.row] - v;
 }
 
 // vertex-indexed coarse solution (0 on Dirichlet vertices)
@@ -643,12 +666,30 @@ coarse_gather_vertex_kernel(double* __restrict__ Rlev, const double* __restrict_
   if (c >= 0) Rlev[c] = Rv[v];
 }
 
-// copy the lower triangle of a column-major n x n matrix to the upper one
-__global__ void symmetrize_kernel(double* __restrict__ A, int64_t n) {
+// --- set-up of the coarse fronts (column-major f x f front F, leading dimension f)
+// copy the lower triangle of the leading n x n block to the upper one
+__global__ void symmetrize_kernel(double* __restrict__ A, int64_t n, int64_t ld) {
   const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (x >= n * n) return;
   const int64_t r = x % n, c = x / n;
-  if (r < c) A[r + c * n] = A[c + r * n];
+  if (r < c) A[r + c * ld] = A[c + r * ld];
+}
+
+// F_IB = F_BI^T: F[c, s + k] = F[s + k, c] for c < s, k < b
+__global__ void front_transpose_kernel(double* __restrict__ F, int64_t f, int64_t s, int64_t b) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= s * b) return;
+  const int64_t c = x % s, k = x / s;
+  F[c + (s + k) * f] = F[(s + k) + c * f];
+}
+
+// extend-add of a child's update matrix U (b x b, leading dimension b) into F
+__global__ void front_extend_add_kernel(double* __restrict__ F, int64_t f, const double* __restrict__ U, int64_t b,
+                                        const int32_t* __restrict__ map) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= b * b) return;
+  const int64_t i = x % b, j = x / b;
+  F[map[i] + (int64_t)map[j] * f] += U[x];
 }
 
 // ---------------------------------------------------------------------------

@@ -862,9 +862,10 @@ void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex)
   });
 }
 
-void build_coarse_levels(HostTables& T) {
+void build_coarse_tree(HostTables& T, int leaf_max) {
   const int N = T.N;
   const int64_t E = T.E, V = T.V;
+  if (leaf_max <= 0) leaf_max = 128;
   // free vertices and their adjacency
   std::vector<int64_t> vid(E * 8);
   for (int64_t e = 0; e < E; ++e)
@@ -874,124 +875,295 @@ void build_coarse_levels(HostTables& T) {
     for (int a = 0; a < 8; ++a)
       for (int b = 0; b < 8; ++b)
         if (a != b) adj[vid[e * 8 + a]].push_back(vid[e * 8 + b]);
-  for (auto& l : adj) {
-    std::sort(l.begin(), l.end());
-    l.erase(std::unique(l.begin(), l.end()), l.end());
-  }
   std::vector<char> freev(V);
   for (int64_t v = 0; v < V; ++v) freev[v] = T.dir[v] == 0;
-  // connected components of the free-vertex graph (a batch of meshes is one
-  // mesh with several components; they never couple)
-  std::vector<int32_t> comp(V, -1);
-  int32_t ncomp = 0;
-  for (int64_t v0 = 0; v0 < V; ++v0) {
-    if (!freev[v0] || comp[v0] >= 0) continue;
-    std::vector<int64_t> stack{v0};
-    comp[v0] = ncomp;
-    while (!stack.empty()) {
-      int64_t v = stack.back();
-      stack.pop_back();
-      for (int64_t w : adj[v])
-        if (freev[w] && comp[w] < 0) {
-          comp[w] = ncomp;
-          stack.push_back(w);
-        }
-    }
-    ++ncomp;
+  for (int64_t v = 0; v < V; ++v) {
+    auto& l = adj[v];
+    std::sort(l.begin(), l.end());
+    l.erase(std::unique(l.begin(), l.end()), l.end());
+    l.erase(std::remove_if(l.begin(), l.end(), [&](int64_t w) { return !freev[w]; }), l.end());
   }
-  // per component: BFS levels from the free vertices nearest the low end of
-  // the mesh's longest axis (plane-shaped levels on box meshes)
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int64_t v = 0; v < V; ++v)
-    for (int r = 0; r < 3; ++r) {
-      lo[r] = std::min(lo[r], T.xN[v * 3 + r]);
-      hi[r] = std::max(hi[r], T.xN[v * 3 + r]);
-    }
-  int ax = 0;
-  for (int r = 1; r < 3; ++r)
-    if (hi[r] - lo[r] > hi[ax] - lo[ax]) ax = r;
-  std::vector<double> hsum(ncomp, 0.0), xmin(ncomp, 1e300);
-  std::vector<int64_t> hcnt(ncomp, 0);
-  for (int64_t e = 0; e < E; ++e)
-    for (int p = 0; p < 8; ++p) {
-      const int32_t c = comp[vid[e * 8 + p]];
-      if (c >= 0) {
-        hsum[c] += T.h[e * 3 + ax];
-        hcnt[c]++;
-        break;
+  // element size along each physical axis (mean extent of the elements'
+  // vertex boxes): extents are measured in element layers, so stretched
+  // meshes are cut across their longest side
+  double hax[3] = {0.0, 0.0, 0.0};
+  for (int64_t e = 0; e < E; ++e) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int p = 0; p < 8; ++p)
+      for (int r = 0; r < 3; ++r) {
+        lo[r] = std::min(lo[r], T.xN[vid[e * 8 + p] * 3 + r]);
+        hi[r] = std::max(hi[r], T.xN[vid[e * 8 + p] * 3 + r]);
       }
+    for (int r = 0; r < 3; ++r) hax[r] += (hi[r] - lo[r]) / (double)E;
+  }
+  for (int r = 0; r < 3; ++r) hax[r] = std::max(hax[r], 1e-300);
+  auto coord = [&](int64_t v, int r) { return T.xN[v * 3 + r]; };
+
+  // --- recursive dissection (explicit task stack; nodes created in pre-order)
+  struct TNode {
+    std::vector<int64_t> own;
+    int32_t parent;
+    std::vector<int32_t> children;
+  };
+  std::vector<TNode> nodes;
+  struct Task {
+    std::vector<int64_t> verts;
+    int32_t parent;
+  };
+  std::vector<Task> tasks;
+  // connected components of the free-vertex graph are independent trees
+  {
+    std::vector<char> seen(V, 0);
+    std::vector<Task> comps;
+    for (int64_t v0 = 0; v0 < V; ++v0) {
+      if (!freev[v0] || seen[v0]) continue;
+      Task t{{v0}, -1};
+      seen[v0] = 1;
+      for (size_t q = 0; q < t.verts.size(); ++q)
+        for (int64_t w : adj[t.verts[q]])
+          if (!seen[w]) {
+            seen[w] = 1;
+            t.verts.push_back(w);
+          }
+      comps.push_back(std::move(t));
     }
-  for (int64_t v = 0; v < V; ++v)
-    if (comp[v] >= 0) xmin[comp[v]] = std::min(xmin[comp[v]], T.xN[v * 3 + ax]);
-  std::vector<int32_t> level(V, -1);
-  int32_t nlev = 0;
-  for (int32_t c = 0; c < ncomp; ++c) {
-    const double hm = hcnt[c] ? hsum[c] / hcnt[c] : 0.0;
-    std::vector<int64_t> front;
-    for (int64_t v = 0; v < V; ++v)
-      if (comp[v] == c && T.xN[v * 3 + ax] <= xmin[c] + 0.5 * hm) front.push_back(v);
-    int32_t cur = 0;
+    // processed in ascending order of their smallest vertex
+    for (auto it = comps.rbegin(); it != comps.rend(); ++it) tasks.push_back(std::move(*it));
+  }
+  std::vector<int64_t> stamp(V, -1), level(V, -1);
+  int64_t tick = 0;
+  auto add_node = [&](std::vector<int64_t> own, int32_t parent) {
+    std::sort(own.begin(), own.end());
+    nodes.push_back(TNode{std::move(own), parent, {}});
+    const int32_t id = (int32_t)nodes.size() - 1;
+    if (parent >= 0) nodes[parent].children.push_back(id);
+    return id;
+  };
+  // BFS levels of `verts` (stamped with `tick`) from `start`; returns the
+  // level sizes, unreached vertices keep level -1
+  auto bfs = [&](const std::vector<int64_t>& start) {
+    std::vector<int64_t> sizes;
+    std::vector<int64_t> front = start;
     for (int64_t v : front) level[v] = 0;
+    int64_t cur = 0;
     while (!front.empty()) {
+      sizes.push_back((int64_t)front.size());
       std::vector<int64_t> next;
       for (int64_t v : front)
         for (int64_t w : adj[v])
-          if (freev[w] && level[w] < 0) {
+          if (stamp[w] == tick && level[w] < 0) {
             level[w] = cur + 1;
             next.push_back(w);
           }
-      std::sort(next.begin(), next.end());
-      next.erase(std::unique(next.begin(), next.end()), next.end());
       ++cur;
       front.swap(next);
     }
-    nlev = std::max(nlev, cur);
-  }
-  // coarse order: by (level, component, vertex id); a level is one contiguous
-  // range, made of one block per component
-  std::vector<int64_t> order;
-  for (int64_t v = 0; v < V; ++v)
-    if (freev[v]) order.push_back(v);
-  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-    if (level[a] != level[b]) return level[a] < level[b];
-    if (comp[a] != comp[b]) return comp[a] < comp[b];
-    return a < b;
-  });
-  T.nc = (int64_t)order.size();
-  T.cidx.assign(V, -1);
-  for (int64_t p = 0; p < T.nc; ++p) T.cidx[order[p]] = (int32_t)p;
-  T.levels.clear();
-  T.blocks.clear();
-  T.row_blk.assign(T.nc, -1);
-  std::vector<int32_t> last_blk(ncomp, -1);
-  int64_t pool = 0;
-  for (int64_t p = 0; p < T.nc;) {
-    const int32_t l = level[order[p]];
-    Level L;
-    L.off = p;
-    L.blk_begin = (int32_t)T.blocks.size();
-    while (p < T.nc && level[order[p]] == l) {
-      const int32_t c = comp[order[p]];
-      Block B;
-      B.off = p;
-      while (p < T.nc && level[order[p]] == l && comp[order[p]] == c) {
-        T.row_blk[p] = (int32_t)T.blocks.size();
-        ++p;
-      }
-      B.size = p - B.off;
-      B.sinv = pool;
-      pool += B.size * B.size;
-      B.prev = last_blk[c];
-      last_blk[c] = (int32_t)T.blocks.size();
-      T.blocks.push_back(B);
+    return sizes;
+  };
+  while (!tasks.empty()) {
+    Task t = std::move(tasks.back());
+    tasks.pop_back();
+    if ((int64_t)t.verts.size() <= leaf_max) {
+      add_node(std::move(t.verts), t.parent);
+      continue;
     }
-    L.size = p - L.off;
-    L.blk_end = (int32_t)T.blocks.size();
-    T.levels.push_back(L);
+    ++tick;
+    for (int64_t v : t.verts) {
+      stamp[v] = tick;
+      level[v] = -1;
+    }
+    // longest extent, in element layers
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t v : t.verts)
+      for (int r = 0; r < 3; ++r) {
+        lo[r] = std::min(lo[r], coord(v, r));
+        hi[r] = std::max(hi[r], coord(v, r));
+      }
+    int ax = 0;
+    for (int r = 1; r < 3; ++r)
+      if ((hi[r] - lo[r]) / hax[r] > (hi[ax] - lo[ax]) / hax[ax]) ax = r;
+    // BFS from the layer of vertices at the low end of that extent
+    std::vector<int64_t> start;
+    for (int64_t v : t.verts)
+      if (coord(v, ax) <= lo[ax] + 0.5 * hax[ax]) start.push_back(v);
+    std::vector<int64_t> sizes = bfs(start);
+    if (sizes.size() < 3) {
+      // too flat for a level cut: restart from the single lowest vertex
+      for (int64_t v : t.verts) level[v] = -1;
+      int64_t v0 = t.verts[0];
+      for (int64_t v : t.verts)
+        if (coord(v, ax) < coord(v0, ax) || (coord(v, ax) == coord(v0, ax) && v < v0)) v0 = v;
+      sizes = bfs({v0});
+    }
+    // vertices the BFS did not reach are not connected to the rest: own task
+    Task rest{{}, t.parent};
+    for (int64_t v : t.verts)
+      if (level[v] < 0) rest.verts.push_back(v);
+    if (sizes.size() < 3) {
+      // no level has vertices on both sides: keep the reached part whole
+      std::vector<int64_t> reached;
+      for (int64_t v : t.verts)
+        if (level[v] >= 0) reached.push_back(v);
+      add_node(std::move(reached), t.parent);
+      if (!rest.verts.empty()) tasks.push_back(std::move(rest));
+      continue;
+    }
+    int64_t reached = 0;
+    for (int64_t c : sizes) reached += c;
+    // separator: the level where the cumulative count passes half (never the
+    // first or the last, so both sides are non-empty)
+    int64_t cut = 1, acc = sizes[0];
+    while (cut + 1 < (int64_t)sizes.size() - 1 && acc + sizes[cut] < (reached + 1) / 2) acc += sizes[cut++];
+    std::vector<int64_t> sep;
+    Task left{{}, -1}, right{{}, -1};
+    for (int64_t v : t.verts) {
+      if (level[v] < 0) continue;
+      if (level[v] == cut)
+        sep.push_back(v);
+      else if (level[v] < cut)
+        left.verts.push_back(v);
+      else
+        right.verts.push_back(v);
+    }
+    const int32_t id = add_node(std::move(sep), t.parent);
+    left.parent = right.parent = id;
+    if (!rest.verts.empty()) tasks.push_back(std::move(rest));
+    tasks.push_back(std::move(right));
+    tasks.push_back(std::move(left));
   }
-  T.sinv_size = pool;
-  // CSR of A_c in level order (assembled from the corner matrices, element order)
-  std::vector<std::vector<std::pair<int32_t, double>>> rows(T.nc);
+
+  // --- post-order numbering
+  const int32_t nn = (int32_t)nodes.size();
+  std::vector<int32_t> post;
+  post.reserve(nn);
+  {
+    std::vector<std::pair<int32_t, size_t>> st;
+    for (int32_t r = 0; r < nn; ++r) {
+      if (nodes[r].parent >= 0) continue;
+      st.push_back({r, 0});
+      while (!st.empty()) {
+        auto& top = st.back();
+        if (top.second < nodes[top.first].children.size()) {
+          const int32_t c = nodes[top.first].children[top.second++];
+          st.push_back({c, 0});
+        } else {
+          post.push_back(top.first);
+          st.pop_back();
+        }
+      }
+    }
+  }
+  std::vector<int32_t> rank(nn);
+  for (int32_t q = 0; q < nn; ++q) rank[post[q]] = q;
+  T.cidx.assign(V, -1);
+  T.fnodes.assign(nn, FrontNode{});
+  T.fchildren.assign(nn, {});
+  int64_t nc = 0;
+  for (int32_t q = 0; q < nn; ++q) {
+    const TNode& tn = nodes[post[q]];
+    FrontNode& F = T.fnodes[q];
+    F.off = nc;
+    F.s = (int32_t)tn.own.size();
+    F.parent = tn.parent >= 0 ? rank[tn.parent] : -1;
+    for (int64_t v : tn.own) T.cidx[v] = (int32_t)nc++;
+    for (int32_t c : tn.children) T.fchildren[q].push_back(rank[c]);
+    std::sort(T.fchildren[q].begin(), T.fchildren[q].end());
+  }
+  T.nc = nc;
+
+  // --- boundary of each node: ancestors coupled to its subtree after elimination
+  std::vector<std::vector<int32_t>> bnd(nn);
+  int32_t maxh = -1;
+  for (int32_t q = 0; q < nn; ++q) {
+    FrontNode& F = T.fnodes[q];
+    const int64_t end = F.off + F.s;
+    std::vector<int32_t> u;
+    for (int64_t v : nodes[post[q]].own)
+      for (int64_t w : adj[v])
+        if (T.cidx[w] >= end) u.push_back(T.cidx[w]);
+    int32_t h = 0;
+    for (int32_t c : T.fchildren[q]) {
+      for (int32_t g : bnd[c])
+        if (g >= end) u.push_back(g);
+      h = std::max(h, T.fnodes[c].height + 1);
+    }
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    F.b = (int32_t)u.size();
+    F.height = h;
+    maxh = std::max(maxh, h);
+    bnd[q] = std::move(u);
+  }
+  // every boundary vertex belongs to an ancestor (the separator property)
+  for (int32_t q = 0; q < nn; ++q) {
+    for (int32_t g : bnd[q]) {
+      int32_t a = T.fnodes[q].parent;
+      while (a >= 0 && !(g >= T.fnodes[a].off && g < T.fnodes[a].off + T.fnodes[a].s)) a = T.fnodes[a].parent;
+      if (a < 0) throw Error{SEM_EMESH, "coarse dissection: boundary vertex outside the ancestors"};
+    }
+  }
+  // --- offsets, contribution lists, per-height work lists, set-up sizes
+  T.fb_idx.clear();
+  int64_t fwd = 0, bwd = 0, coff = 0;
+  int32_t mf = 0;
+  for (int32_t q = 0; q < nn; ++q) {
+    FrontNode& F = T.fnodes[q];
+    F.bidx = (int64_t)T.fb_idx.size();
+    T.fb_idx.insert(T.fb_idx.end(), bnd[q].begin(), bnd[q].end());
+    F.fwd = fwd;
+    F.bwd = bwd;
+    F.coff = coff;
+    fwd += (int64_t)(F.s + F.b) * F.s;
+    bwd += (int64_t)F.s * F.b;
+    coff += F.b;
+    mf = std::max(mf, F.s + F.b);
+  }
+  T.fwd_size = fwd;
+  T.bwd_size = bwd;
+  T.c_size = coff;
+  T.max_front = mf;
+  T.ct_off.assign(nc + 1, 0);
+  for (int32_t q = 0; q < nn; ++q)
+    for (int32_t g : bnd[q]) T.ct_off[g + 1]++;
+  for (int64_t r = 0; r < nc; ++r) T.ct_off[r + 1] += T.ct_off[r];
+  T.ct_pos.assign(T.ct_off[nc], 0);
+  {
+    std::vector<int32_t> fill(T.ct_off.begin(), T.ct_off.end() - 1);
+    for (int32_t q = 0; q < nn; ++q)  // ascending node: fixed subtraction order
+      for (int32_t k = 0; k < T.fnodes[q].b; ++k)
+        T.ct_pos[fill[bnd[q][k]]++] = (int32_t)(T.fnodes[q].coff + k);
+  }
+  T.n_heights = maxh + 1;
+  T.fy_off.assign(T.n_heights + 1, 0);
+  T.fr_off.assign(T.n_heights + 1, 0);
+  T.br_off.assign(T.n_heights + 1, 0);
+  T.fy_items.clear();
+  T.fr_items.clear();
+  T.br_items.clear();
+  for (int32_t h = 0; h < T.n_heights; ++h) {
+    for (int32_t q = 0; q < nn; ++q) {
+      const FrontNode& F = T.fnodes[q];
+      if (F.height != h) continue;
+      for (int32_t r = 0; r < F.s; ++r) T.fy_items.push_back((int32_t)(F.off + r));
+      for (int32_t r = 0; r < F.s + F.b; ++r) T.fr_items.push_back(RowItem{q, r});
+      for (int32_t r = 0; r < F.s; ++r) T.br_items.push_back(RowItem{q, r});
+    }
+    T.fy_off[h + 1] = (int32_t)T.fy_items.size();
+    T.fr_off[h + 1] = (int64_t)T.fr_items.size();
+    T.br_off[h + 1] = (int64_t)T.br_items.size();
+  }
+  // largest sum of update matrices waiting for their parent (post-order stack)
+  {
+    int64_t cur = 0, mx = 0;
+    for (int32_t q = 0; q < nn; ++q) {
+      for (int32_t c : T.fchildren[q]) cur -= (int64_t)T.fnodes[c].b * T.fnodes[c].b;
+      cur += (int64_t)T.fnodes[q].b * T.fnodes[q].b;
+      mx = std::max(mx, cur);
+    }
+    T.ustack_size = mx;
+  }
+  // --- CSR of A_c in coarse order (assembled from the corner matrices, element order)
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(nc);
   for (int64_t e = 0; e < E; ++e)
     for (int a = 0; a < 8; ++a) {
       int32_t ra = T.cidx[vid[e * 8 + a]];
@@ -1002,10 +1174,10 @@ void build_coarse_levels(HostTables& T) {
         rows[ra].push_back({cb, T.corner_K[e * 64 + a * 8 + b]});
       }
     }
-  T.ac_off.assign(T.nc + 1, 0);
+  T.ac_off.assign(nc + 1, 0);
   T.ac_col.clear();
   T.ac_val.clear();
-  for (int64_t r = 0; r < T.nc; ++r) {
+  for (int64_t r = 0; r < nc; ++r) {
     auto& l = rows[r];
     std::stable_sort(l.begin(), l.end(), [](auto& x, auto& y) { return x.first < y.first; });
     for (size_t q = 0; q < l.size(); ++q) {
@@ -1017,35 +1189,6 @@ void build_coarse_levels(HostTables& T) {
       }
     }
     T.ac_off[r + 1] = (int32_t)T.ac_col.size();
-  }
-  // coupling lists of each row towards the previous and the next level
-  std::vector<int64_t> lev_of(T.nc);
-  for (size_t l = 0; l < T.levels.size(); ++l)
-    for (int64_t r = T.levels[l].off; r < T.levels[l].off + T.levels[l].size; ++r) lev_of[r] = (int64_t)l;
-  T.lo_off.assign(T.nc + 1, 0);
-  T.up_off.assign(T.nc + 1, 0);
-  T.lo_col.clear();
-  T.up_col.clear();
-  T.lo_val.clear();
-  T.up_val.clear();
-  for (int64_t r = 0; r < T.nc; ++r) {
-    const Level& L = T.levels[lev_of[r]];
-    for (int32_t q = T.ac_off[r]; q < T.ac_off[r + 1]; ++q) {
-      // components never couple, and levels couple only to neighbours
-      if (T.row_blk[T.ac_col[q]] != T.row_blk[r] && T.blocks[T.row_blk[T.ac_col[q]]].prev != T.row_blk[r] &&
-          T.blocks[T.row_blk[r]].prev != T.row_blk[T.ac_col[q]])
-        throw Error{SEM_EMESH, "coarse level structure broken"};
-      const int32_t c = T.ac_col[q];
-      if (c < L.off) {
-        T.lo_col.push_back(c);
-        T.lo_val.push_back(T.ac_val[q]);
-      } else if (c >= L.off + L.size) {
-        T.up_col.push_back(c);
-        T.up_val.push_back(T.ac_val[q]);
-      }
-    }
-    T.lo_off[r + 1] = (int32_t)T.lo_col.size();
-    T.up_off[r + 1] = (int32_t)T.up_col.size();
   }
 }
 
