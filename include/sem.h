@@ -68,7 +68,9 @@ typedef struct {
 typedef struct {
   int mode;          /* sem_solve_mode */
   int pc;            /* sem_pc */
-  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2 (recursive residual for FP64) */
+  double rtol;       /* stop when ||b - A x||_2 <= rtol ||b||_2; FP64 checks the recursive residual
+                        each iteration, then confirms with the true residual and restarts from it
+                        while it is above the tolerance */
   int max_iter;      /* FP64: iteration cap; refined: cap on inner iterations per outer step */
   int use_x0;        /* 1: start from the x passed in, else x = 0 */
   double inner_rtol; /* refined form: relative tolerance of each FP32 inner solve */
@@ -78,8 +80,9 @@ typedef struct {
 
 typedef struct {
   int iterations;        /* total PCG iterations (inner iterations summed for the refined form) */
-  int outer_iterations;  /* refined form: number of FP64 residual corrections */
-  double rel_residual;   /* final ||r||_2 / ||b||_2 (true FP64 residual for the refined form) */
+  int outer_iterations;  /* refined form: number of FP64 residual corrections; FP64: restarts
+                            from the true residual */
+  double rel_residual;   /* final ||r||_2 / ||b||_2 (the true FP64 residual when converged) */
   double solve_ms;       /* wall time of the solve on the host clock */
   double* history;       /* optional caller buffer for ||r_k|| / ||b|| (may be NULL) */
   int history_cap;

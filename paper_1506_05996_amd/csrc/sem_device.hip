@@ -604,6 +604,31 @@ int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, 
     }
     SEM_HIP(hipGetLastError());
     status = pcg_core<double>(m, x, r, bnorm2, o->rtol, o->max_iter, o->pc, check, s, &iters, &rel, st);
+    // the recursive residual can drift below the true one: confirm with
+    // b - A x and restart from the true residual while it is above the tolerance
+    const double tol2 = o->rtol * o->rtol * bnorm2;
+    double* Ax = m->v64[4].p;
+    while (status == SEM_OK) {
+      apply_A<double>(m, x, Ax, s);
+      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r, b, Ax, m->part.p, n);
+      hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 8, 0);
+      SEM_HIP(hipGetLastError());
+      const double rr = read_scalar(m, 8, s);
+      rel = std::sqrt(rr / bnorm2);
+      if (!std::isfinite(rr)) {
+        status = SEM_EBREAKDOWN;
+        break;
+      }
+      if (rr <= tol2) break;
+      if (iters >= o->max_iter) {
+        status = SEM_ENOCONV;
+        break;
+      }
+      ++outer;
+      int it = 0;
+      status = pcg_core<double>(m, x, r, bnorm2, o->rtol, o->max_iter - iters, o->pc, check, s, &it, &rel, st);
+      iters += it;
+    }
   } else {
     // outer FP64 refinement around FP32 inner PCG solves
     double* r64 = m->v64[1].p;
