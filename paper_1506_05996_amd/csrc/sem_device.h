@@ -62,15 +62,16 @@ struct sem_mesh_s {
   bool fp32 = true;
   int device = 0;
   // numbering / gather
-  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, owner, cidx, order;
+  DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, cidx, order;
   DBuf<uint8_t> dir, fcount;
   // operator
   DBuf<double> G64, D64, w64;
   DBuf<float> G32, D32, w32;
   // fine preconditioner
-  DBuf<int32_t> ip, ip_off, ip_slot;
-  DBuf<double> S64, lam64, h64, zP64;
-  DBuf<float> S32, lam32, h32, zP32;
+  // patch corrections: zo = [zc: E x (N+1)^3 own nodes | zx: E x nx consumer layout]
+  DBuf<int32_t> ip, xord, xdest;
+  DBuf<double> S64, lam64, h64, zo64;
+  DBuf<float> S32, lam32, h32, zo32;
   // coarse: vectors in coarse order (R, y, Z, X), vertex-order solution Zv,
   // the nested-dissection fronts and their work lists
   DBuf<double> phi, Re, Rlev, Ylev, Wlev, Xlev, Zv;

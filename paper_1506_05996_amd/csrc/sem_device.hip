@@ -51,11 +51,11 @@ double* Wp<double>(sem_mesh m) { return m->w64.p; }
 template <>
 float* Wp<float>(sem_mesh m) { return m->w32.p; }
 template <typename T>
-T* ZPp(sem_mesh m);
+T* ZOp(sem_mesh m);
 template <>
-double* ZPp<double>(sem_mesh m) { return m->zP64.p; }
+double* ZOp<double>(sem_mesh m) { return m->zo64.p; }
 template <>
-float* ZPp<float>(sem_mesh m) { return m->zP32.p; }
+float* ZOp<float>(sem_mesh m) { return m->zo32.p; }
 template <typename T>
 const T* Sp(sem_mesh m);
 template <>
@@ -168,9 +168,39 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
 // --- fine and coarse preconditioner -----------------------------------------
 template <int N, typename T>
 void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
-  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r,
-                     ZPp<T>(m), m->ip.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E);
+  T* zc = ZOp<T>(m);
+  T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
+  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
+                     m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E);
   SEM_HIP(hipGetLastError());
+}
+
+// element-wise sum of the corrections (+ coarse interpolation) into z and w
+template <int N, typename T>
+void launch_schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s) {
+  constexpr int EPB = ax_epb<N>();
+  const T* zc = ZOp<T>(m);
+  const T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
+  const int64_t grid = xcd_grid((m->T.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((schwarz_sum_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, z,
+                     Wp<T>(m), zc, zx, m->rec.p, m->dir.p, m->order.p, m->T.E, (int)fine, Zv, m->phi.p);
+  SEM_HIP(hipGetLastError());
+}
+
+template <typename T>
+void schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s) {
+  switch (m->T.N) {
+#define CASE(NN)                                        \
+  case NN:                                              \
+    launch_schwarz_sum<NN, T>(m, z, fine, Zv, s);       \
+    break;
+    CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+    CASE(15)
+#undef CASE
+    default:
+      throw Error{SEM_EUNSUPPORTED, "order not compiled"};
+  }
+  launch_gs<T>(m, z, s);
 }
 
 template <int N, typename T>
@@ -290,10 +320,7 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     SEM_HIP(hipEventRecord(m->ev_join, sc));
     SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
   }
-  hipLaunchKernelGGL((precond_gather_kernel<T>), dim3((unsigned)blocks_for(H.n_global)), dim3(kGS), 0, s, z,
-                     (const T*)ZPp<T>(m), m->ip_off.p, m->ip_slot.p, m->dir.p, H.n_global, (int)fine,
-                     coarse ? (const double*)m->Zv.p : nullptr, m->owner.p, m->rec.p, m->phi.p, H.N);
-  SEM_HIP(hipGetLastError());
+  schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s);
 }
 
 // --- coarse factorisation (set-up), multifrontal in post-order.  Node t's
@@ -432,7 +459,6 @@ void upload_all(sem_mesh m) {
   m->order.upload(T.order.data(), T.order.size());
   m->vinc_off.upload(T.vinc_off.data(), T.vinc_off.size());
   m->einc_off.upload(T.einc_off.data(), T.einc_off.size());
-  m->owner.upload(T.owner.data(), T.owner.size());
   m->dir.upload(T.dir.data(), T.dir.size());
   m->fcount.upload(T.fcount.data(), T.fcount.size());
   {
@@ -451,12 +477,14 @@ void upload_all(sem_mesh m) {
   m->D64.upload(T.D.data(), T.D.size());
   m->w64.alloc(T.w_size);
   m->ip.upload(T.ip.data(), T.ip.size());
-  m->ip_off.upload(T.ip_off.data(), T.ip_off.size());
-  m->ip_slot.upload(T.ip_slot.data(), T.ip_slot.size());
+  m->xord.upload(T.xord.data(), T.xord.size());
+  m->xdest.upload(T.xdest.data(), T.xdest.size());
   m->S64.upload(T.S.data(), T.S.size());
   m->lam64.upload(T.lam.data(), T.lam.size());
   m->h64.upload(T.h.data(), T.h.size());
-  m->zP64.alloc((size_t)T.E * T.np * T.np * T.np);
+  // consumer slots no patch writes (NULL) stay zero for good
+  m->zo64.alloc((size_t)T.E * T.np * T.np * T.np);
+  SEM_HIP(hipMemset(m->zo64.p, 0, m->zo64.n * sizeof(double)));
   if (m->fp32) {
     auto G32 = convert<float>(T.G);
     m->G32.upload(G32.data(), G32.size());
@@ -469,7 +497,8 @@ void upload_all(sem_mesh m) {
     m->lam32.upload(l32.data(), l32.size());
     auto h32 = convert<float>(T.h);
     m->h32.upload(h32.data(), h32.size());
-    m->zP32.alloc((size_t)T.E * T.np * T.np * T.np);
+    m->zo32.alloc((size_t)T.E * T.np * T.np * T.np);
+    SEM_HIP(hipMemset(m->zo32.p, 0, m->zo32.n * sizeof(float)));
   }
   // Phi_I(t_i): row I = 0, 1
   std::vector<double> phi(2 * T.n1);

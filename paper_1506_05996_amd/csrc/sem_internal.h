@@ -88,7 +88,17 @@ struct HostTables {
   // faces and patches
   std::vector<int32_t> face_nbr;         // [E][6][2] (element, local face) or -1
   std::vector<int32_t> ip;               // [E][(N+3)^3] global id or -1
-  std::vector<int32_t> ip_off, ip_slot;  // inverse of ip (CSR over global ids, slots ascending)
+  // the nx = (N+3)^3 - (N+1)^3 patch slots outside the element: their ordinal
+  // (xord[slot] >= 0; inside: -(local index) - 1) and, per patch, where each
+  // lands in the consumer layout [E][nx] of the element that holds it:
+  // 6 face planes [(N+1)^2] at one layer in from that face (in-plane index
+  // x_lo + (N+1) x_hi over the other two axes in increasing order), 12 edge
+  // lines [N+1] at one layer in from both faces of the edge (edge id
+  // 4 axis + side_lo + 2 side_hi, position along the axis), 8 corner points
+  // (id = side_x + 2 side_y + 4 side_z); -1 where the slot is NULL
+  int64_t nx = 0;
+  std::vector<int32_t> xord;             // [(N+3)^3]
+  std::vector<int32_t> xdest;            // [E][nx]
 
   // geometry
   std::vector<double> G;     // [E][6][(N+1)^3]

@@ -312,7 +312,9 @@ gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict_
 // Fine patch solve, eq. (z), one workgroup per subdomain.  The (N+3)^3 patch
 // is gathered through I^p into LDS; each of the six 1D contractions is done
 // by lanes that own a whole pencil in registers (one LDS read and one write
-// per node and pass); the diagonal scaling is fused into the zeta pass.
+// per node and pass); the diagonal scaling is fused into the zeta pass.  The
+// correction at the element's own nodes goes to zc; the slots outside the
+// element go to the consumer layout of the element that holds them (zx).
 // ---------------------------------------------------------------------------
 template <int N>
 constexpr int fdm_threads() {
@@ -321,9 +323,9 @@ constexpr int fdm_threads() {
 
 template <int N, typename T>
 __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
-fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restrict__ ip,
-           const T* __restrict__ S, const T* __restrict__ lam, const T* __restrict__ hg,
-           const int32_t* __restrict__ order, int64_t E) {
+fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
+           const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
+           const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E) {
   // S and lambda are read with wave-uniform indices (scalar loads)
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
@@ -430,70 +432,133 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zP, const int32_t* __restric
     }
   }
   __syncthreads();
-  T* zPe = zP + e * MMM;
-  for (int x = tid; x < MMM; x += NT) zPe[x] = X[x];
+  // the element's own nodes to zc (element-local order); the slots outside it
+  // to the consumer layout of the elements that hold them (NULL slots dropped)
+  {
+    constexpr int R = (MMM + NT - 1) / NT, NX = MMM - (N + 1) * (N + 1) * (N + 1);
+    T* zce = zc + e * (MMM - NX);
+    const int32_t* xd = xdest + e * NX;
+    int32_t o[R], d[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) o[q] = (tid + q * NT < MMM) ? xord[tid + q * NT] : -1;
+#pragma unroll
+    for (int q = 0; q < R; ++q) d[q] = o[q] >= 0 ? xd[o[q]] : -1;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      if (tid + q * NT >= MMM) continue;
+      const T v = X[tid + q * NT];
+      if (o[q] < 0)
+        zce[-o[q] - 1] = v;
+      else if (d[q] >= 0)
+        zx[d[q]] = v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Additive accumulation P^f[I^p] += z_s (slots of each global node summed in
-// ascending order), plus the coarse prolongation (I Z)_N evaluated at the
-// node's first local copy, then the Dirichlet mask.
+// Sum of the patch corrections and the coarse interpolation, element by element
+// (the preconditioner's result before assembly).  Lane (i, j) of element e
+// walks its k-pencil: the patch of e itself (zc) plus the corrections that the
+// neighbouring patches left in e's consumer layout (zx: planes one layer in
+// from each face, lines one layer in from both faces of each edge, corner
+// points), then I Z at the nodes e owns.  Element interiors go straight to z
+// (Dirichlet zeroed), shared nodes to the work array for gs_kernel.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
-precond_gather_kernel(T* __restrict__ z, const T* __restrict__ zP, const int32_t* __restrict__ ip_off,
-                      const int32_t* __restrict__ ip_slot, const uint8_t* __restrict__ dir, int64_t ng,
-                      int use_fine, const double* __restrict__ Zv, const int32_t* __restrict__ owner,
-                      const int32_t* __restrict__ rec, const double* __restrict__ phi, int N) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= ng) return;
-  // Loads go out chain by chain with no wait inside a level: slot range and
-  // owner, then up to kPre slots and the 8 vertex records, then the patch
-  // values and coarse values.
-  constexpr int kPre = 8;
-  T s = 0;
-  int32_t q0 = 0, q1 = 0;
+template <int N, typename T, int EPB>
+__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
+schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ zc, const T* __restrict__ zx,
+                   const int32_t* __restrict__ rec, const uint8_t* __restrict__ dir,
+                   const int32_t* __restrict__ order, int64_t E, int use_fine, const double* __restrict__ Zv,
+                   const double* __restrict__ phi) {
+  constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
+  constexpr int NX = (N + 3) * (N + 3) * (N + 3) - NN;
+  constexpr int F0 = 0, E0 = 6 * P, C0 = 6 * P + 12 * n1;
+  constexpr int RX = (NX + P - 1) / P;
+  __shared__ T sX[EPB][NX];  // the element's consumer layout, staged with coalesced loads
+  __shared__ double sPhi[2 * n1];
+  const int tid = threadIdx.x;
+  const int le = tid / P, ij = tid - le * P;
+  const int i = ij % n1, j = ij / n1;
+  const int64_t pos = xcd_position(blockIdx.x, (E + EPB - 1) / EPB) * EPB + le;
+  const bool valid = pos < E;
+  const int64_t e = valid ? order[pos] : 0;
+  const int cx = node_class(i, N), cy = node_class(j, N);
+  const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+  const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
+  const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+  T cv[n1];
   if (use_fine) {
-    q0 = ip_off[g];
-    q1 = ip_off[g + 1];
-  }
-  int32_t o = 0;
-  if (Zv != nullptr) o = owner[g];
-  int32_t sl[kPre];
+    const T* ze = zc + e * NN;
+    const T* xe = zx + e * NX;
+    T xv[RX];
 #pragma unroll
-  for (int t = 0; t < kPre; ++t) sl[t] = (q0 + t < q1) ? ip_slot[q0 + t] : -1;
-  const int n1 = N + 1, nn = n1 * n1 * n1;
-  const int64_t e = o / nn;
-  int32_t vid[8];
+    for (int q = 0; q < RX; ++q) xv[q] = (ij + q * P < NX) ? xe[ij + q * P] : T(0);
+#pragma unroll
+    for (int k = 0; k < n1; ++k) cv[k] = ze[ij + P * k];
+#pragma unroll
+    for (int q = 0; q < RX; ++q)
+      if (ij + q * P < NX) sX[le][ij + q * P] = xv[q];
+  }
+  double zv[8];
   if (Zv != nullptr) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int cls = 2 * (c & 1) + 6 * ((c >> 1) & 1) + 18 * (c >> 2);
-      vid[c] = rec[(e * kClasses + cls) * kRecInts];
+      zv[c] = Zv[rec[(e * kClasses + cls) * kRecInts]];
     }
+    for (int x = tid; x < 2 * n1; x += EPB * P) sPhi[x] = phi[x];
   }
-  T pv[kPre];
+  __syncthreads();
+  if (!valid) return;
+  const T* xs = sX[le];
+  const bool li0 = i == 1, li1 = i == N - 1, lj0 = j == 1, lj1 = j == N - 1;
 #pragma unroll
-  for (int t = 0; t < kPre; ++t) pv[t] = zP[sl[t] >= 0 ? sl[t] : 0];
+  for (int k = 0; k < n1; ++k) {
+    const bool lk0 = k == 1, lk1 = k == N - 1;
+    T v = 0;
+    if (use_fine) {
+      v = cv[k];
+      if (li0) v += xs[F0 + 0 * P + j + n1 * k];
+      if (li1) v += xs[F0 + 1 * P + j + n1 * k];
+      if (lj0) v += xs[F0 + 2 * P + i + n1 * k];
+      if (lj1) v += xs[F0 + 3 * P + i + n1 * k];
+      if (lk0) v += xs[F0 + 4 * P + i + n1 * j];
+      if (lk1) v += xs[F0 + 5 * P + i + n1 * j];
+      // edge lines along x (sides of y, z), along y (sides of x, z), along z (sides of x, y)
+      if (lj0 && lk0) v += xs[E0 + (0 + 0 + 0) * n1 + i];
+      if (lj1 && lk0) v += xs[E0 + (0 + 1 + 0) * n1 + i];
+      if (lj0 && lk1) v += xs[E0 + (0 + 0 + 2) * n1 + i];
+      if (lj1 && lk1) v += xs[E0 + (0 + 1 + 2) * n1 + i];
+      if (li0 && lk0) v += xs[E0 + (4 + 0 + 0) * n1 + j];
+      if (li1 && lk0) v += xs[E0 + (4 + 1 + 0) * n1 + j];
+      if (li0 && lk1) v += xs[E0 + (4 + 0 + 2) * n1 + j];
+      if (li1 && lk1) v += xs[E0 + (4 + 1 + 2) * n1 + j];
+      if (li0 && lj0) v += xs[E0 + (8 + 0 + 0) * n1 + k];
+      if (li1 && lj0) v += xs[E0 + (8 + 1 + 0) * n1 + k];
+      if (li0 && lj1) v += xs[E0 + (8 + 0 + 2) * n1 + k];
+      if (li1 && lj1) v += xs[E0 + (8 + 1 + 2) * n1 + k];
 #pragma unroll
-  for (int t = 0; t < kPre; ++t)
-    if (sl[t] >= 0) s += pv[t];
-  for (int32_t q = q0 + kPre; q < q1; ++q) s += zP[ip_slot[q]];
-  if (Zv != nullptr) {
-    double zc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) zc[c] = Zv[vid[c]];
-    const int loc = o - (int)e * nn;
-    const int i = loc % n1, j = (loc / n1) % n1, k = loc / (n1 * n1);
-    double acc = 0.0;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int I = c & 1, J = (c >> 1) & 1, K = c >> 2;
-      acc += phi[I * n1 + i] * phi[J * n1 + j] * phi[K * n1 + k] * zc[c];
+      for (int c = 0; c < 8; ++c) {
+        const bool si = (c & 1) ? li1 : li0, sj = ((c >> 1) & 1) ? lj1 : lj0, sk = (c >> 2) ? lk1 : lk0;
+        if (si && sj && sk) v += xs[C0 + c];
+      }
     }
-    s += (T)acc;
+    const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
+    if (Zv != nullptr && (rr.w & kFlagOwned)) {
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        acc += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * zv[c];
+      v += (T)acc;
+    }
+    int ai, aj, ak;
+    unpack_coef(rr.y, ai, aj, ak);
+    const int off = ai * i + aj * j + ak * k;
+    if (rr.w & kFlagInterior)
+      z[rr.x + off] = (masked_interior && dir[rr.x + off]) ? T(0) : v;
+    else
+      w[rr.z + off] = v;
   }
-  z[g] = dir[g] ? T(0) : s;
 }
 
 // Coarse restriction, per element: R_e[IJK] = sum over the nodes this element
@@ -504,10 +569,12 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
                 const double* __restrict__ phi, const int32_t* __restrict__ order, int64_t E) {
   constexpr int n1 = N + 1, P = n1 * n1;
   __shared__ double red[8][P];
+  __shared__ double sPhi[2 * n1];
   const int tid = threadIdx.x;
   const int i = tid % n1, j = tid / n1;
   const int64_t pos = xcd_position(blockIdx.x, E);
-  if (pos >= E) return;
+  if (pos >= E) return;  // whole workgroup
+  for (int x = tid; x < 2 * n1; x += P) sPhi[x] = phi[x];
   const int64_t e = order[pos];
   const int cx = node_class(i, N), cy = node_class(j, N);
   // the three records of the lane's k-pencil, then all its residual values
@@ -521,6 +588,7 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
     unpack_coef(rr.y, ai, aj, ak);
     rv[k] = r[rr.x + ai * i + aj * j + ak * k];
   }
+  __syncthreads();
   double acc[8];
 #pragma unroll
   for (int c = 0; c < 8; ++c) acc[c] = 0.0;
@@ -531,7 +599,7 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
       const double v = (double)rv[k];
 #pragma unroll
       for (int c = 0; c < 8; ++c)
-        acc[c] += phi[(c & 1) * n1 + i] * phi[((c >> 1) & 1) * n1 + j] * phi[(c >> 2) * n1 + k] * v;
+        acc[c] += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * v;
     }
   }
 #pragma unroll

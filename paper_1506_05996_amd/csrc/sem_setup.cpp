@@ -10,6 +10,7 @@
 //    makes it block tridiagonal (Section 4.1).
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -735,6 +736,39 @@ void build_patches(HostTables& T, const int64_t* hex) {
     return 0;
   };
   T.ip.assign((size_t)E * pp, -1);
+  // patch slots outside the element: ordinal among them, or -(local index)-1 inside
+  const int n1 = N + 1;
+  const int64_t nx = pp - (int64_t)n1 * n1 * n1;
+  T.nx = nx;
+  T.xord.assign(pp, 0);
+  {
+    int32_t o = 0;
+    for (int c = 0; c < np; ++c)
+      for (int b = 0; b < np; ++b)
+        for (int a = 0; a < np; ++a) {
+          const int x = a + np * (b + np * c);
+          if (a >= 1 && a <= N + 1 && b >= 1 && b <= N + 1 && c >= 1 && c <= N + 1)
+            T.xord[x] = -((a - 1) + n1 * ((b - 1) + n1 * (c - 1))) - 1;
+          else
+            T.xord[x] = o++;
+        }
+  }
+  // consumer slot of an outside patch slot: the element it lands in receives it
+  // in its own frame, at one layer in from the face / edge / corner it shares
+  // with the patch's element
+  T.xdest.assign((size_t)E * nx, -1);
+  const int64_t fplane = (int64_t)n1 * n1;
+  auto other_axes = [](int d, int& lo, int& hi) {
+    lo = d == 0 ? 1 : 0;
+    hi = d == 2 ? 1 : 2;
+  };
+  auto local_corner = [&](int64_t e, int64_t v) {
+    for (int q = 0; q < 8; ++q)
+      if (hex[e * 8 + q] == v) return q;
+    return -1;
+  };
+  auto layer1 = [&](int v, int side) { return v == (side ? N - 1 : 1); };
+  std::atomic<bool> off_layer{false};
   parallel_for(E, [&](int64_t b0, int64_t b1) {
     for (int64_t s = b0; s < b1; ++s) {
       for (int c = 0; c < np; ++c)
@@ -770,6 +804,18 @@ void build_patches(HostTables& T, const int64_t* hex) {
             }
             int64_t e = s;
             bool valid = true;
+            int entry = -1;  // face of the landing element through which the last step entered
+            int64_t ev0 = -1, ev1 = -1;  // mesh edge (nout = 2) or vertex (nout = 3) shared with the patch
+            if (nout == 2) {
+              int dfree = (x[0] >= 0 && x[0] <= N) ? 0 : ((x[1] >= 0 && x[1] <= N) ? 1 : 2);
+              int c0[3] = {corner[0], corner[1], corner[2]}, c1[3] = {corner[0], corner[1], corner[2]};
+              c0[dfree] = 0;
+              c1[dfree] = 1;
+              ev0 = hex[s * 8 + corner_pos(c0[0], c0[1], c0[2])];
+              ev1 = hex[s * 8 + corner_pos(c1[0], c1[1], c1[2])];
+            } else if (nout == 3) {
+              ev0 = hex[s * 8 + corner_pos(corner[0], corner[1], corner[2])];
+            }
             for (int step = 0; step < 4; ++step) {
               int d = -1;
               for (int q = 0; q < 3; ++q)
@@ -790,22 +836,51 @@ void build_patches(HostTables& T, const int64_t* hex) {
               x[0] = y[0];
               x[1] = y[1];
               x[2] = y[2];
+              entry = T.face_nbr[(e * 6 + lf) * 2 + 1];
               e = e2;
             }
-            if (valid) T.ip[(size_t)s * pp + a + np * (b + np * c)] = (int32_t)gid_of(T, e, x[0], x[1], x[2]);
+            if (!valid) continue;
+            const int slot = a + np * (b + np * c);
+            T.ip[(size_t)s * pp + slot] = (int32_t)gid_of(T, e, x[0], x[1], x[2]);
+            if (nout == 0) continue;
+            int64_t cs = -1;
+            if (nout == 1) {
+              const int d = kFaceAxis[entry], side = kFaceSide[entry];
+              int lo, hi;
+              other_axes(d, lo, hi);
+              if (layer1(x[d], side)) cs = entry * fplane + x[lo] + (int64_t)n1 * x[hi];
+            } else if (nout == 2) {
+              const int pa = local_corner(e, ev0), pb = local_corner(e, ev1);
+              if (pa >= 0 && pb >= 0 && __builtin_popcount(pa ^ pb) == 1) {
+                const int ax = __builtin_ctz(pa ^ pb);
+                int lo, hi;
+                other_axes(ax, lo, hi);
+                const int slo = (pa >> lo) & 1, shi = (pa >> hi) & 1;
+                if (layer1(x[lo], slo) && layer1(x[hi], shi))
+                  cs = 6 * fplane + (int64_t)(ax * 4 + slo + 2 * shi) * n1 + x[ax];
+              }
+            } else {
+              const int pc = local_corner(e, ev0);
+              if (pc >= 0 && layer1(x[0], pc & 1) && layer1(x[1], (pc >> 1) & 1) && layer1(x[2], (pc >> 2) & 1))
+                cs = 6 * fplane + 12 * (int64_t)n1 + pc;
+            }
+            if (cs < 0) {
+              off_layer = true;
+              continue;
+            }
+            T.xdest[(size_t)s * nx + T.xord[slot]] = (int32_t)(e * nx + cs);
           }
     }
   });
-  // inverse table: for every global node, the patch slots that hold it, ascending
-  T.ip_off.assign(T.n_global + 1, 0);
-  for (size_t x = 0; x < T.ip.size(); ++x)
-    if (T.ip[x] >= 0) T.ip_off[T.ip[x] + 1]++;
-  for (int64_t g = 0; g < T.n_global; ++g) T.ip_off[g + 1] += T.ip_off[g];
-  if ((int64_t)T.ip.size() >= (int64_t)INT32_MAX) throw Error{SEM_EUNSUPPORTED, "patch table too large"};
-  T.ip_slot.assign(T.ip_off[T.n_global], 0);
-  std::vector<int32_t> fill(T.ip_off.begin(), T.ip_off.end() - 1);
-  for (size_t x = 0; x < T.ip.size(); ++x)
-    if (T.ip[x] >= 0) T.ip_slot[fill[T.ip[x]]++] = (int32_t)x;
+  if (off_layer) throw Error{SEM_EMESH, "patch slot lands off the expected layer"};
+  if ((int64_t)E * nx >= (int64_t)INT32_MAX) throw Error{SEM_EUNSUPPORTED, "patch table too large"};
+  // every consumer slot is filled by at most one patch
+  std::vector<uint8_t> hit((size_t)E * nx, 0);
+  for (int32_t d : T.xdest)
+    if (d >= 0) {
+      if (hit[d]) throw Error{SEM_EMESH, "two patches write one consumer slot"};
+      hit[d] = 1;
+    }
 }
 
 // ---------------------------------------------------------------------------
