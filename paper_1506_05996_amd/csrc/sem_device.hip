@@ -295,8 +295,10 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     return;
   }
   // The coarse and fine parts are independent until the final sum: the
-  // coarse chain (restriction, level sweeps) runs on a second stream while the
-  // patch solves run on the caller's stream; both join before the gather.
+  // coarse chain (restriction, coarse sweeps) runs on a second stream while
+  // the patch solves run on the caller's stream; both join before the sum.
+  // The patch solves are issued first, so that the host's launches of the
+  // coarse chain do not hold them back.
   hipStream_t sc = s;
   if (coarse && fine) {
     if (!m->side_stream) {
@@ -308,6 +310,7 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     SEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
     sc = m->side_stream;
   }
+  if (fine) fdm_and_restrict<T>(m, r, true, false, s);
   if (coarse) {
     fdm_and_restrict<T>(m, r, false, true, sc);
     hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, sc, m->Rlev.p, m->Re.p,
@@ -315,7 +318,6 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     SEM_HIP(hipGetLastError());
     coarse_solve_levels(m, sc);
   }
-  if (fine) fdm_and_restrict<T>(m, r, true, false, s);
   if (sc != s) {
     SEM_HIP(hipEventRecord(m->ev_join, sc));
     SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));

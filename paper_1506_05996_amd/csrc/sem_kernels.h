@@ -321,17 +321,48 @@ constexpr int fdm_threads() {
   return (((N + 3) * (N + 3) + 63) / 64) * 64;
 }
 
+// one 1D pass of the fast diagonalisation on a lane's pencil, S (m x m,
+// row-major) read from LDS a row at a time.  The outer loop stays rolled so
+// that S is not hoisted into registers.
+//   pencil_St: out[b] = sum_a S[a][b] x[a stride]     (x in LDS)
+//   pencil_S:  y[a stride] = scale sum_b S[a][b] v[b]  (y in LDS)
+template <int m, typename T>
+__device__ __forceinline__ void pencil_St(const T* __restrict__ sS, const T* x, int stride, T (&out)[m]) {
+#pragma unroll
+  for (int b = 0; b < m; ++b) out[b] = T(0);
+#pragma unroll 1
+  for (int a = 0; a < m; ++a) {
+    const T va = x[a * stride];
+    const T* sr = sS + a * m;
+#pragma unroll
+    for (int b = 0; b < m; ++b) out[b] += sr[b] * va;
+  }
+}
+
+template <int m, typename T>
+__device__ __forceinline__ void pencil_S(const T* __restrict__ sS, const T (&v)[m], T* y, int stride, T scale) {
+#pragma unroll 1
+  for (int a = 0; a < m; ++a) {
+    const T* sr = sS + a * m;
+    T acc = T(0);
+#pragma unroll
+    for (int b = 0; b < m; ++b) acc += sr[b] * v[b];
+    y[a * stride] = acc * scale;
+  }
+}
+
 template <int N, typename T>
 __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
            const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
            const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E) {
-  // S and lambda are read with wave-uniform indices (scalar loads)
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
+  __shared__ T sS[MM];
+  __shared__ T sL[m];
   const int tid = threadIdx.x;
   const int64_t pos = xcd_position(blockIdx.x, E);
-  if (pos >= E) return;
+  if (pos >= E) return;  // whole workgroup
   const int64_t e = order[pos];
   const int32_t* ipe = ip + e * MMM;
   {
@@ -343,6 +374,8 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T rv[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) rv[q] = r[gi[q] >= 0 ? gi[q] : 0];
+    for (int x = tid; x < MM; x += NT) sS[x] = S[x];
+    if (tid < m) sL[tid] = lam[tid];
 #pragma unroll
     for (int q = 0; q < R; ++q)
       if (tid + q * NT < MMM) X[tid + q * NT] = gi[q] >= 0 ? rv[q] : T(0);
@@ -357,51 +390,27 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   // pass 1: xi, S^T   (lane owns row (b = p0, c = p1))
   if (act) {
     T* row = X + p1 * MM + p0 * m;
+    pencil_St<m, T>(sS, row, 1, o);
 #pragma unroll
-    for (int a = 0; a < m; ++a) v[a] = row[a];
-#pragma unroll
-    for (int a2 = 0; a2 < m; ++a2) {
-      T s = 0;
-#pragma unroll
-      for (int a = 0; a < m; ++a) s += S[a * m + a2] * v[a];
-      row[a2] = s;
-    }
+    for (int a = 0; a < m; ++a) row[a] = o[a];
   }
   __syncthreads();
   // pass 2: eta, S^T  (lane owns column (a = p0, c = p1))
   if (act) {
     T* col = X + p1 * MM + p0;
+    pencil_St<m, T>(sS, col, m, o);
 #pragma unroll
-    for (int b = 0; b < m; ++b) v[b] = col[b * m];
-#pragma unroll
-    for (int b2 = 0; b2 < m; ++b2) {
-      T s = 0;
-#pragma unroll
-      for (int b = 0; b < m; ++b) s += S[b * m + b2] * v[b];
-      col[b2 * m] = s;
-    }
+    for (int b = 0; b < m; ++b) col[b * m] = o[b];
   }
   __syncthreads();
   // pass 3: zeta, S^T, diagonal, S  (lane owns pencil (a = p0, b = p1))
   if (act) {
     T* pen = X + p1 * m + p0;
+    const T dab = sL[p0] * ihx2 + sL[p1] * ihy2;
+    pencil_St<m, T>(sS, pen, MM, o);
 #pragma unroll
-    for (int c = 0; c < m; ++c) v[c] = pen[c * MM];
-    const T dab = lam[p0] * ihx2 + lam[p1] * ihy2;
-#pragma unroll
-    for (int c2 = 0; c2 < m; ++c2) {
-      T s = 0;
-#pragma unroll
-      for (int c = 0; c < m; ++c) s += S[c * m + c2] * v[c];
-      o[c2] = s / (dab + lam[c2] * ihz2);
-    }
-#pragma unroll
-    for (int c = 0; c < m; ++c) {
-      T s = 0;
-#pragma unroll
-      for (int c2 = 0; c2 < m; ++c2) s += S[c * m + c2] * o[c2];
-      pen[c * MM] = s;
-    }
+    for (int c = 0; c < m; ++c) o[c] = o[c] / (dab + sL[c] * ihz2);
+    pencil_S<m, T>(sS, o, pen, MM, T(1));
   }
   __syncthreads();
   // pass 4: eta, S
@@ -409,13 +418,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T* col = X + p1 * MM + p0;
 #pragma unroll
     for (int b = 0; b < m; ++b) v[b] = col[b * m];
-#pragma unroll
-    for (int b = 0; b < m; ++b) {
-      T s = 0;
-#pragma unroll
-      for (int b2 = 0; b2 < m; ++b2) s += S[b * m + b2] * v[b2];
-      col[b * m] = s;
-    }
+    pencil_S<m, T>(sS, v, col, m, T(1));
   }
   __syncthreads();
   // pass 5: xi, S, and the volume factor 8/(hx hy hz)
@@ -423,13 +426,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T* row = X + p1 * MM + p0 * m;
 #pragma unroll
     for (int a = 0; a < m; ++a) v[a] = row[a];
-#pragma unroll
-    for (int a = 0; a < m; ++a) {
-      T s = 0;
-#pragma unroll
-      for (int a2 = 0; a2 < m; ++a2) s += S[a * m + a2] * v[a2];
-      row[a] = s * vscale;
-    }
+    pencil_S<m, T>(sS, v, row, 1, vscale);
   }
   __syncthreads();
   // the element's own nodes to zc (element-local order); the slots outside it
