@@ -85,6 +85,70 @@ def cpu_baseline(mesh, N, n_global, budget_s=10.0, sample_elems=4096):
                       f"(N={N}), {reps} reps in {el:.1f} s, {t * 1e3:.1f} ms/apply, scaled by elements"}
 
 
+def run_batch(args):
+    """64 independent solves of uneven size and order in one batched call
+    (FP64 and FP32-refined, to a relative residual of 1e-10), against the same
+    instances solved one after another through sem_pcg_solve."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    dev = torch.device("cuda:0")
+    inst = meshgen.batch_instances(64)
+    t0 = time.time()
+    B = sem.Batch([(d["mesh"].vtx, d["mesh"].hex, d["N"]) for d in inst])
+    setup_s = time.time() - t0
+    total = int(sum(B.n_global))
+    log(f"[bench] batch: 64 instances, {total} DOFs, orders {sorted(set(d['N'] for d in inst))}, "
+        f"set-up {setup_s:.1f} s")
+    bs = []
+    for d in inst:
+        H = sem.Mesh(d["mesh"].vtx, d["mesh"].hex, d["N"], host_only=True)
+        b = d["rhs"].copy()
+        b[H.boundary_mask().astype(bool)] = 0.0
+        H.close()
+        bs.append(torch.tensor(b, device=dev))
+    res = {}
+    for name, mode in (("fp64", sem.SOLVE_FP64), ("fp32_refined", sem.SOLVE_FP32_REFINED)):
+        B.solve(bs, mode=mode, rtol=1e-10, max_iter=2000, inner_rtol=1e-2, max_outer=40)  # warm-up, graph capture
+        times = []
+        for _ in range(max(1, args.pcg_reps)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            xs, infos, status = B.solve(bs, mode=mode, rtol=1e-10, max_iter=2000, inner_rtol=1e-2, max_outer=40)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+        its = [i["iterations"] for i in infos]
+        res[name] = {"time_s": round(float(np.median(times)), 4), "status": status,
+                     "iterations_max": max(its), "iterations_mean": round(float(np.mean(its)), 1),
+                     "rel_residual_max": max(i["rel_residual"] for i in infos)}
+        log(f"[bench] batch {name}: {res[name]}")
+    # the same instances one after another
+    if not args.no_serial:
+        serial = 0.0
+        for d, b in zip(inst, bs):
+            M = sem.Mesh(d["mesh"].vtx, d["mesh"].hex, d["N"])
+            M.solve(b, rtol=1e-10, max_iter=2000)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            M.solve(b, rtol=1e-10, max_iter=2000)
+            torch.cuda.synchronize()
+            serial += time.perf_counter() - t1
+            M.close()
+        res["fp64_one_by_one_s"] = round(serial, 4)
+        res["batch_speedup_fp64"] = round(serial / res["fp64"]["time_s"], 3)
+        log(f"[bench] one by one fp64: {serial:.3f} s")
+    out = {"metric": "batched PCG time-to-1e-10, 64 instances (DOF/s, FP64)",
+           "value": round(total / res["fp64"]["time_s"], 1), "unit": "DOF/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batch64", "instances": 64, "total_dofs": total, "setup_s": round(setup_s, 2),
+                      "orders": [d["N"] for d in inst], "k": [d["k"] for d in inst]},
+           "pcg": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +158,7 @@ def main():
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pcg-reps", type=int, default=1)
+    ap.add_argument("--no-serial", action="store_true", help="batch64: skip the one-by-one comparison")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     args = ap.parse_args()
@@ -101,6 +166,10 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        run_batch(args)
+        return
 
     import numpy as np
     import torch
