@@ -322,8 +322,9 @@ constexpr int fdm_threads() {
 }
 
 // one 1D pass of the fast diagonalisation on a lane's pencil, S (m x m,
-// row-major) read from LDS a row at a time.  The outer loop stays rolled so
-// that S is not hoisted into registers.
+// row-major, in global memory) read a row at a time with wave-uniform
+// addresses (scalar loads feeding the FMAs directly).  The outer loop stays
+// rolled so that S is not hoisted into registers.
 //   pencil_St: out[b] = sum_a S[a][b] x[a stride]     (x in LDS)
 //   pencil_S:  y[a stride] = scale sum_b S[a][b] v[b]  (y in LDS)
 template <int m, typename T>
@@ -358,7 +359,6 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
            const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E) {
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
-  __shared__ T sS[MM];
   __shared__ T sL[m];
   const int tid = threadIdx.x;
   const int64_t pos = xcd_position(blockIdx.x, E);
@@ -374,7 +374,6 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T rv[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) rv[q] = r[gi[q] >= 0 ? gi[q] : 0];
-    for (int x = tid; x < MM; x += NT) sS[x] = S[x];
     if (tid < m) sL[tid] = lam[tid];
 #pragma unroll
     for (int q = 0; q < R; ++q)
@@ -390,7 +389,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   // pass 1: xi, S^T   (lane owns row (b = p0, c = p1))
   if (act) {
     T* row = X + p1 * MM + p0 * m;
-    pencil_St<m, T>(sS, row, 1, o);
+    pencil_St<m, T>(S, row, 1, o);
 #pragma unroll
     for (int a = 0; a < m; ++a) row[a] = o[a];
   }
@@ -398,7 +397,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   // pass 2: eta, S^T  (lane owns column (a = p0, c = p1))
   if (act) {
     T* col = X + p1 * MM + p0;
-    pencil_St<m, T>(sS, col, m, o);
+    pencil_St<m, T>(S, col, m, o);
 #pragma unroll
     for (int b = 0; b < m; ++b) col[b * m] = o[b];
   }
@@ -407,10 +406,10 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   if (act) {
     T* pen = X + p1 * m + p0;
     const T dab = sL[p0] * ihx2 + sL[p1] * ihy2;
-    pencil_St<m, T>(sS, pen, MM, o);
+    pencil_St<m, T>(S, pen, MM, o);
 #pragma unroll
     for (int c = 0; c < m; ++c) o[c] = o[c] / (dab + sL[c] * ihz2);
-    pencil_S<m, T>(sS, o, pen, MM, T(1));
+    pencil_S<m, T>(S, o, pen, MM, T(1));
   }
   __syncthreads();
   // pass 4: eta, S
@@ -418,7 +417,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T* col = X + p1 * MM + p0;
 #pragma unroll
     for (int b = 0; b < m; ++b) v[b] = col[b * m];
-    pencil_S<m, T>(sS, v, col, m, T(1));
+    pencil_S<m, T>(S, v, col, m, T(1));
   }
   __syncthreads();
   // pass 5: xi, S, and the volume factor 8/(hx hy hz)
@@ -426,7 +425,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     T* row = X + p1 * MM + p0 * m;
 #pragma unroll
     for (int a = 0; a < m; ++a) v[a] = row[a];
-    pencil_S<m, T>(sS, v, row, 1, vscale);
+    pencil_S<m, T>(S, v, row, 1, vscale);
   }
   __syncthreads();
   // the element's own nodes to zc (element-local order); the slots outside it
