@@ -571,14 +571,16 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   double rr = bnorm2;
   int status = SEM_ENOCONV;
   if (rr <= tol2) status = SEM_OK;
+  bool pending_x = false;  // x += alpha p of the last iteration not yet applied
   while (status != SEM_OK && k < max_iter) {
     apply_A<T>(m, p, w, s);
     dot<T, T>(m, p, w, 1, 1, s);
-    hipLaunchKernelGGL((update_xr_kernel<T, T>), dim3(nb), dim3(kRedThreads), 0, s, x, r, p, w, m->sc.p, m->part.p,
-                       n);
+    hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)m->sc.p,
+                       m->part.p, n);
     SEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 4, 0);
     ++k;
+    pending_x = true;
     if (k % check_every == 0 || k == max_iter) {
       rr = read_scalar(m, 4, s);
       const double flag = read_scalar(m, 6, s);
@@ -595,7 +597,12 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
     }
     precond<T>(m, r, z, pc, s);
     dot<T, T>(m, r, z, 5, 2, s);
-    hipLaunchKernelGGL((update_p_kernel<T>), dim3(gb), dim3(kGS), 0, s, p, z, m->sc.p, n);
+    hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)m->sc.p, n);
+    SEM_HIP(hipGetLastError());
+    pending_x = false;
+  }
+  if (pending_x) {
+    hipLaunchKernelGGL((update_x_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, (const T*)p, (const double*)m->sc.p, n);
     SEM_HIP(hipGetLastError());
   }
   *iters = k;

@@ -809,17 +809,16 @@ dot_final_kernel(const double* __restrict__ part, double* __restrict__ sc, int n
   }
 }
 
-// x += alpha p; r -= alpha w; partial sums of r^T r
-template <typename T, typename TX>
+// r -= alpha w; partial sums of r^T r (the matching x update is deferred to
+// update_px_kernel, which reads p anyway)
+template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
-update_xr_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ w,
-                 const double* __restrict__ sc, double* __restrict__ part, int64_t n) {
+update_r_kernel(T* __restrict__ r, const T* __restrict__ w, const double* __restrict__ sc, double* __restrict__ part,
+                int64_t n) {
   __shared__ double sh[kRedThreads / 64];
-  const double alpha = sc[2];
-  const T al = (T)alpha;
+  const T al = (T)sc[2];
   double s = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-    x[q] += (TX)(al * p[q]);
     const T rn = r[q] - al * w[q];
     r[q] = rn;
     s += (double)rn * (double)rn;
@@ -828,13 +827,27 @@ update_xr_kernel(TX* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// p = z + beta p
+// x += alpha p (this iteration's alpha); p = z + beta p
 template <typename T>
 __global__ void __launch_bounds__(256)
-update_p_kernel(T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ sc, int64_t n) {
+update_px_kernel(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ sc,
+                 int64_t n) {
+  const T al = (T)sc[2];
   const T beta = (T)sc[3];
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
+    const T pq = p[q];
+    x[q] += al * pq;
+    p[q] = z[q] + beta * pq;
+  }
+}
+
+// x += alpha p (the last iteration's deferred update)
+template <typename T>
+__global__ void __launch_bounds__(256)
+update_x_kernel(T* __restrict__ x, const T* __restrict__ p, const double* __restrict__ sc, int64_t n) {
+  const T al = (T)sc[2];
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
-    p[q] = z[q] + beta * p[q];
+    x[q] += al * p[q];
 }
 
 template <typename TD, typename TS>
