@@ -78,7 +78,7 @@ struct sem_mesh_s {
   DBuf<double> fwd_pool, bwd_pool, cvec;
   DBuf<FrontNode> fnodes;
   DBuf<int32_t> fb_idx, ct_off, ct_pos, fy_items;
-  DBuf<RowItem> fr_items, br_items;
+  DBuf<RowItem> fr_items, br_items, fs_items;
   hipGraphExec_t coarse_graph = nullptr;  // the solve sweeps, captured once per factorisation
   bool direct_coarse = false;             // launch the sweeps directly (inside an enclosing capture)
   int epb[2] = {0, 0};                    // operator tile (elements per workgroup) for FP64, FP32

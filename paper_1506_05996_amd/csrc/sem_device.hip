@@ -232,12 +232,18 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
   const int H = T.n_heights;
   for (int h = 0; h < H; ++h) {
     const int64_t ny = T.fy_off[h + 1] - T.fy_off[h], nr = T.fr_off[h + 1] - T.fr_off[h];
-    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)blocks_for(ny)), dim3(kGS), 0, s, m->Ylev.p,
+    const int64_t ns = T.fs_off[h + 1] - T.fs_off[h];
+    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)blocks_for(8 * ny)), dim3(kGS), 0, s, m->Ylev.p,
                        (const double*)m->Rlev.p, (const double*)m->cvec.p, m->ct_off.p, m->ct_pos.p,
                        m->fy_items.p + T.fy_off[h], ny);
-    hipLaunchKernelGGL(coarse_fwd_kernel, dim3((unsigned)((nr + 3) / 4)), dim3(256), 0, s, m->Wlev.p, m->cvec.p,
-                       (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
-                       m->fr_items.p + T.fr_off[h], nr);
+    if (ns > 0)
+      hipLaunchKernelGGL(coarse_fwd_small_kernel, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, s, m->Wlev.p,
+                         m->cvec.p, (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
+                         m->fs_items.p + T.fs_off[h], ns);
+    if (nr > 0)
+      hipLaunchKernelGGL(coarse_fwd_kernel, dim3((unsigned)((nr + 3) / 4)), dim3(256), 0, s, m->Wlev.p, m->cvec.p,
+                         (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
+                         m->fr_items.p + T.fr_off[h], nr);
     SEM_HIP(hipGetLastError());
   }
   for (int h = H - 1; h >= 0; --h) {
@@ -354,6 +360,7 @@ void factor_coarse(sem_mesh m) {
   m->fy_items.upload(T.fy_items.data(), T.fy_items.size());
   m->fr_items.upload(T.fr_items.data(), T.fr_items.size());
   m->br_items.upload(T.br_items.data(), T.br_items.size());
+  m->fs_items.upload(T.fs_items.data(), T.fs_items.size());
   m->cvec.alloc(std::max<int64_t>(T.c_size, 1));
   m->fwd_pool.alloc(T.fwd_size);
   m->bwd_pool.alloc(std::max<int64_t>(T.bwd_size, 1));
@@ -424,27 +431,38 @@ void factor_coarse(sem_mesh m) {
       throw Error{SEM_EHIP, "rocsolver_dpotri failed"};
     hipLaunchKernelGGL(symmetrize_kernel, dim3((unsigned)blocks_for(s * s)), dim3(kGS), 0, 0, Fd.p, s, f);
     SEM_HIP(hipGetLastError());
-    // forward matrix [S^-1 ; W] row-major = column-major s x (s + b): [S^-1 | W^T]
+    // Large node: forward [S^-1 ; W] row-major = column-major s x (s + b):
+    // [S^-1 | W^T].  Small node: forward [S^-1 ; W] column-major (ld s + b).
+    // Backward, every node: W^T row-major = W column-major (ld b).
     double* X = m->fwd_pool.p + F.fwd;
-    SEM_HIP(hipMemcpy2D(X, s * sizeof(double), Fd.p, f * sizeof(double), s * sizeof(double), s,
+    double* Wb = m->bwd_pool.p + F.bwd;
+    const int64_t ldx = F.small ? f : s;
+    SEM_HIP(hipMemcpy2D(X, ldx * sizeof(double), Fd.p, f * sizeof(double), s * sizeof(double), s,
                         hipMemcpyDeviceToDevice));
     if (b > 0) {
       const rocblas_int si = (rocblas_int)s, bi = (rocblas_int)b, fi = (rocblas_int)f;
-      // W^T = S^-1 F_IB  (s x b)
-      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, si, bi, si, &one, Fd.p, fi,
-                        Fd.p + s * f, fi, &zero, X + s * s, si) != rocblas_status_success)
-        throw Error{SEM_EHIP, "rocblas_dgemm failed"};
-      // W = F_BI S^-1  (b x b... b x s, column-major = row-major W^T for the backward sweep)
-      double* Wb = m->bwd_pool.p + F.bwd;
+      // W = F_BI S^-1  (b x s), column-major (ld b) for the backward sweep
+      double* W = Wb;
+      const rocblas_int ldw = bi;
       if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, bi, si, si, &one, Fd.p + s, fi, Fd.p,
-                        fi, &zero, Wb, bi) != rocblas_status_success)
+                        fi, &zero, W, ldw) != rocblas_status_success)
         throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      if (F.small) {
+        // forward rows s.. of the column-major [S^-1; W]
+        SEM_HIP(hipMemcpy2D(X + s, f * sizeof(double), W, b * sizeof(double), b * sizeof(double), s,
+                            hipMemcpyDeviceToDevice));
+      } else {
+        // W^T = S^-1 F_IB  (s x b), the forward columns s..
+        if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, si, bi, si, &one, Fd.p, fi,
+                          Fd.p + s * f, fi, &zero, X + s * s, si) != rocblas_status_success)
+          throw Error{SEM_EHIP, "rocblas_dgemm failed"};
+      }
       // U = F_BB - W F_IB, pushed for the parent
       if (top + b * b > std::max<int64_t>(T.ustack_size, 1)) throw Error{SEM_EHIP, "coarse update stack overflow"};
       double* U = Ust.p + top;
       SEM_HIP(hipMemcpy2D(U, b * sizeof(double), Fd.p + s + s * f, f * sizeof(double), b * sizeof(double), b,
                           hipMemcpyDeviceToDevice));
-      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, bi, bi, si, &mone, Wb, bi, Fd.p + s * f,
+      if (rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, bi, bi, si, &mone, W, ldw, Fd.p + s * f,
                         fi, &one, U, bi) != rocblas_status_success)
         throw Error{SEM_EHIP, "rocblas_dgemm failed"};
       u_at[q] = top;

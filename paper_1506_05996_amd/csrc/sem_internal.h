@@ -48,9 +48,16 @@ inline int32_t pack_coef(int ai, int aj, int ak) {
 // the boundary B: the vertices of its ancestors coupled to its subtree once
 // the subtree is eliminated.  After elimination of the subtree, the front
 // [F_II F_IB; F_BI F_BB] gives S = F_II and W = F_BI S^-1.
+// Nodes with s <= kSmallFront are "small": their forward product runs one lane
+// per row (the forward matrix is stored transposed so that lanes read
+// consecutive rows); larger nodes, and every backward product, use one wave
+// per row.
+constexpr int kSmallFront = 128;
+
 struct FrontNode {
   int64_t off;     // first coarse index of the node's own vertices
-  int64_t fwd;     // offset of [S^-1 ; W] ((s + b) x s, row-major) in the forward pool
+  int64_t fwd;     // offset of [S^-1 ; W] in the forward pool: (s + b) x s row-major,
+                   // or column-major (leading dimension s + b) for a small node
   int64_t bwd;     // offset of W^T (s x b, row-major) in the backward pool
   int64_t bidx;    // offset of the boundary list (ascending coarse indices) in fb_idx
   int64_t coff;    // offset of the node's contribution W y in the contribution vector
@@ -58,6 +65,8 @@ struct FrontNode {
   int32_t b;       // boundary vertices
   int32_t parent;  // -1 for a root
   int32_t height;  // 0 for a leaf, else 1 + the largest height of its children
+  int32_t small;   // 1 when s <= kSmallFront
+  int32_t pad;
 };
 
 // one row of a per-height work list: (node, row or column of that node)
@@ -122,8 +131,10 @@ struct HostTables {
   int32_t max_front = 0;                 // largest s + b
   int32_t n_heights = 0;
   std::vector<int32_t> fy_off, fy_items;  // per height: coarse rows to assemble
-  std::vector<int64_t> fr_off, br_off;    // per height: ranges of fr_items / br_items
+  std::vector<int64_t> fr_off, br_off;    // per height: ranges of fr_items (large nodes) / br_items (all)
   std::vector<RowItem> fr_items, br_items;  // forward rows (s + b per node), backward columns (s per node)
+  std::vector<int64_t> fs_off;            // per height: range of fs_items (small nodes)
+  std::vector<RowItem> fs_items;          // 64-row chunks of small nodes' forward rows
   std::vector<double> corner_K;          // [E][8][8] order-1 element matrices
 };
 

@@ -637,17 +637,23 @@ restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, co
 //     X_I = Z_I - W_t^T X_B
 // All rows are independent within a height; sums run in a fixed order.
 
-// y_i = R_i - sum of the contributions listed for row i (ascending node)
+// y_i = R_i - sum of the contributions listed for row i: 8 lanes per row,
+// lane t taking every 8th entry from t, then a fixed shuffle tree
 __global__ void __launch_bounds__(256)
 coarse_assemble_kernel(double* __restrict__ Y, const double* __restrict__ R, const double* __restrict__ cvec,
                        const int32_t* __restrict__ ct_off, const int32_t* __restrict__ ct_pos,
                        const int32_t* __restrict__ items, int64_t n) {
-  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (x >= n) return;
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t x = gid >> 3;
+  const int sub = (int)(gid & 7);
+  if (x >= n) return;  // whole 8-lane groups leave together
   const int32_t i = items[x];
-  double s = R[i];
-  for (int32_t q = ct_off[i]; q < ct_off[i + 1]; ++q) s -= cvec[ct_pos[q]];
-  Y[i] = s;
+  double s = 0.0;
+  for (int32_t q = ct_off[i] + sub; q < ct_off[i + 1]; q += 8) s += cvec[ct_pos[q]];
+  s += __shfl_xor(s, 4, 8);
+  s += __shfl_xor(s, 2, 8);
+  s += __shfl_xor(s, 1, 8);
+  if (sub == 0) Y[i] = R[i] - s;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -684,6 +690,50 @@ coarse_fwd_kernel(double* __restrict__ Z, double* __restrict__ cvec, const doubl
     else
       cvec[nd.coff + ri.row - nd.s] = v;
   }
+}
+
+// value of v held by lane l (l wave-uniform)
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l), hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// small nodes (s <= 128): one lane per row of [S^-1; W] (column-major,
+// leading dimension s + b), 64-row chunks; y sits in two registers per lane
+// and is broadcast with readlane; matrix loads go out eight at a time
+__global__ void __launch_bounds__(256)
+coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ Y,
+                        const double* __restrict__ pool, const FrontNode* __restrict__ nodes,
+                        const RowItem* __restrict__ items, int64_t n) {
+  const int64_t it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
+  const int lane = threadIdx.x & 63;
+  if (it >= n) return;  // whole wave
+  const RowItem ri = items[it];
+  const FrontNode nd = nodes[ri.node];
+  const int f = nd.s + nd.b, s = nd.s;
+  const int rho = ri.row * 64 + lane;
+  const int rr = rho < f ? rho : f - 1;
+  const double* M = pool + nd.fwd + rr;
+  const double* y = Y + nd.off;
+  const double y0 = lane < s ? y[lane] : 0.0;
+  const double y1 = lane + 64 < s ? y[lane + 64] : 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < s; c0 += 8) {
+    double mv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) mv[u] = M[(int64_t)(c0 + u < s ? c0 + u : s - 1) * f];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = c0 + u;
+      if (c < s) acc[u & 3] += mv[u] * lane_value(c < 64 ? y0 : y1, c & 63);
+    }
+  }
+  const double v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  if (rho < s)
+    Z[nd.off + rho] = v;
+  else if (rho < f)
+    cvec[nd.coff + rho - s] = v;
 }
 
 // one wave per own column c of a node: X_c = Z_c - (W^T)_c . X_B

@@ -1188,6 +1188,7 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
     F.fwd = fwd;
     F.bwd = bwd;
     F.coff = coff;
+    F.small = F.s <= kSmallFront ? 1 : 0;
     fwd += (int64_t)(F.s + F.b) * F.s;
     bwd += (int64_t)F.s * F.b;
     coff += F.b;
@@ -1212,20 +1213,26 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
   T.fy_off.assign(T.n_heights + 1, 0);
   T.fr_off.assign(T.n_heights + 1, 0);
   T.br_off.assign(T.n_heights + 1, 0);
+  T.fs_off.assign(T.n_heights + 1, 0);
   T.fy_items.clear();
   T.fr_items.clear();
   T.br_items.clear();
+  T.fs_items.clear();
   for (int32_t h = 0; h < T.n_heights; ++h) {
     for (int32_t q = 0; q < nn; ++q) {
       const FrontNode& F = T.fnodes[q];
       if (F.height != h) continue;
       for (int32_t r = 0; r < F.s; ++r) T.fy_items.push_back((int32_t)(F.off + r));
-      for (int32_t r = 0; r < F.s + F.b; ++r) T.fr_items.push_back(RowItem{q, r});
+      if (F.small)
+        for (int32_t r = 0; r < (F.s + F.b + 63) / 64; ++r) T.fs_items.push_back(RowItem{q, r});
+      else
+        for (int32_t r = 0; r < F.s + F.b; ++r) T.fr_items.push_back(RowItem{q, r});
       for (int32_t r = 0; r < F.s; ++r) T.br_items.push_back(RowItem{q, r});
     }
     T.fy_off[h + 1] = (int32_t)T.fy_items.size();
     T.fr_off[h + 1] = (int64_t)T.fr_items.size();
     T.br_off[h + 1] = (int64_t)T.br_items.size();
+    T.fs_off[h + 1] = (int64_t)T.fs_items.size();
   }
   // largest sum of update matrices waiting for their parent (post-order stack)
   {
