@@ -88,7 +88,7 @@ struct sem_mesh_s {
   // PCG work
   DBuf<double> v64[5];
   DBuf<float> v32[5];
-  DBuf<double> part, sc;
+  DBuf<double> part, sc, dpart;
 };
 
 namespace sem {

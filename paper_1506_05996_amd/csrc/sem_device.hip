@@ -86,38 +86,43 @@ constexpr bool tile_ok(int epb) {
   return epb * (N + 1) * (N + 1) <= 1024;
 }
 
+// element kernel launches; with dpart, each workgroup also leaves its share
+// of u . y over the element interiors in dpart[block] (the grid size is
+// returned so the caller knows how many)
 template <int N, typename T, int EPB>
-void launch_ax_tile(sem_mesh m, const T* u, T* y, hipStream_t s) {
+int64_t launch_ax_tile(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   if constexpr (tile_ok<N>(EPB)) {
     const HostTables& T_ = m->T;
     const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
     hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
-                       Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
+                       Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart);
     SEM_HIP(hipGetLastError());
+    return grid;
   } else {
     throw Error{SEM_EINVAL, "operator tile too large for the order"};
   }
 }
 
 template <int N, typename T>
-void launch_ax(sem_mesh m, const T* u, T* y, hipStream_t s) {
+int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   const int epb = m->epb[std::is_same<T, double>::value ? 0 : 1];
   if (epb == kTileMfma) {
     if constexpr (N == 15 && std::is_same<T, double>::value) {
       const HostTables& T_ = m->T;
-      hipLaunchKernelGGL(ax_mfma15_kernel, dim3((unsigned)xcd_grid(T_.E)), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
-                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E);
+      const int64_t grid = xcd_grid(T_.E);
+      hipLaunchKernelGGL(ax_mfma15_kernel, dim3((unsigned)grid), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
+                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart);
       SEM_HIP(hipGetLastError());
-      return;
+      return grid;
     } else {
       throw Error{SEM_EINVAL, "the matrix-core operator exists for FP64 at N = 15"};
     }
   }
   switch (epb > 0 ? epb : ax_epb<N>()) {
-    case 1: launch_ax_tile<N, T, 1>(m, u, y, s); break;
-    case 2: launch_ax_tile<N, T, 2>(m, u, y, s); break;
-    case 4: launch_ax_tile<N, T, 4>(m, u, y, s); break;
-    case 8: launch_ax_tile<N, T, 8>(m, u, y, s); break;
+    case 1: return launch_ax_tile<N, T, 1>(m, u, y, dpart, s);
+    case 2: return launch_ax_tile<N, T, 2>(m, u, y, dpart, s);
+    case 4: return launch_ax_tile<N, T, 4>(m, u, y, dpart, s);
+    case 8: return launch_ax_tile<N, T, 8>(m, u, y, dpart, s);
     default: throw Error{SEM_EINVAL, "operator tile"};
   }
 }
@@ -135,22 +140,23 @@ int default_tile(int N) {
 }
 
 template <typename T>
-void launch_gs(sem_mesh m, T* y, hipStream_t s) {
+int64_t launch_gs(sem_mesh m, T* y, hipStream_t s, const T* pd = nullptr, double* dpart = nullptr) {
   const HostTables& T_ = m->T;
-  hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)blocks_for(T_.base_i)), dim3(kGS), 0, s, y, Wp<T>(m),
-                     m->vinc_off.p, m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1,
-                     T_.wedge_off, T_.wvert_off);
+  const int64_t grid = blocks_for(T_.base_i);
+  hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)grid), dim3(kGS), 0, s, y, Wp<T>(m), m->vinc_off.p,
+                     m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1, T_.wedge_off,
+                     T_.wvert_off, pd, dpart);
   SEM_HIP(hipGetLastError());
+  return grid;
 }
 
-// element kernel only (the gather follows separately)
+// element kernel only (the gather follows separately); returns the grid size
 template <typename T>
-void apply_A_elements(sem_mesh m, const T* u, T* y, hipStream_t s) {
+int64_t apply_A_elements(sem_mesh m, const T* u, T* y, hipStream_t s, double* dpart = nullptr) {
   switch (m->T.N) {
 #define CASE(NN) \
   case NN:       \
-    launch_ax<NN, T>(m, u, y, s); \
-    break;
+    return launch_ax<NN, T>(m, u, y, dpart, s);
     CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
     CASE(15)
 #undef CASE
@@ -163,6 +169,21 @@ template <typename T>
 void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
   apply_A_elements<T>(m, u, y, s);
   launch_gs<T>(m, y, s);
+}
+
+// y = A u and u . y into the scalar slot dst (dot_final mode `mode`), the dot
+// product taken from the operator's own kernels (no extra pass over u and y)
+template <typename T>
+void apply_A_dot(sem_mesh m, const T* u, T* y, int dst, int mode, hipStream_t s) {
+  const int64_t na = apply_A_elements<T>(m, u, y, s, m->dpart.p);
+  const int64_t ng = launch_gs<T>(m, y, s, u, m->dpart.p + na);
+  const int64_t n = na + ng;
+  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const int nb = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->dpart.p, m->part.p, n,
+                     chunk);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dst, mode);
+  SEM_HIP(hipGetLastError());
 }
 
 // --- fine and coarse preconditioner -----------------------------------------
@@ -538,6 +559,10 @@ void ensure_work(sem_mesh m, bool need32) {
   const int64_t n = m->T.n_global;
   for (auto& b : m->v64)
     if (b.n != (size_t)n) b.alloc(n);
+  // partial dot products of the operator (one per element workgroup at most,
+  // one per gather workgroup)
+  const size_t nd = (size_t)(xcd_grid(m->T.E) + blocks_for(m->T.base_i));
+  if (m->dpart.n < nd) m->dpart.alloc(nd);
   if (need32)
     for (auto& b : m->v32)
       if (b.n != (size_t)n) b.alloc(n);
@@ -591,8 +616,7 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   if (rr <= tol2) status = SEM_OK;
   bool pending_x = false;  // x += alpha p of the last iteration not yet applied
   while (status != SEM_OK && k < max_iter) {
-    apply_A<T>(m, p, w, s);
-    dot<T, T>(m, p, w, 1, 1, s);
+    apply_A_dot<T>(m, p, w, 1, 1, s);
     hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)m->sc.p,
                        m->part.p, n);
     SEM_HIP(hipGetLastError());

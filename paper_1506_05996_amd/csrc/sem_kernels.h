@@ -41,6 +41,34 @@ __device__ __forceinline__ T pick(const T (&a)[M], int k) {
   return r;
 }
 
+// Sum of v over a workgroup of NT lanes in a fixed order (deterministic):
+// wave shuffles when NT is a multiple of 64, else a tree in LDS (red[NT]).
+// Every lane of the workgroup must call it; lane 0 gets the result.
+template <int NT>
+__device__ __forceinline__ double group_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  if constexpr (NT % 64 == 0) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (tid == 0)
+      for (int q = 0; q < NT / 64; ++q) s += red[q];
+    return s;
+  } else {
+    constexpr int P2 = NT >= 512 ? 512 : NT >= 256 ? 256 : NT >= 128 ? 128 : NT >= 64 ? 64 : NT >= 32 ? 32 : NT >= 16 ? 16 : 8;
+    red[tid] = v;
+    __syncthreads();
+    if (tid < NT - P2) red[tid] += red[tid + P2];
+    __syncthreads();
+    for (int h = P2 / 2; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    return red[0];
+  }
+}
+
 // global id and work slot of lane (i, j)'s node in plane k, from the records
 struct NodeAddr {
   int g, w, flags;
@@ -69,9 +97,10 @@ template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1)) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
           const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
-          const int32_t* __restrict__ order, int64_t E) {
+          const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   __shared__ T sD[P];
+  __shared__ double sRed[EPB * P];
   __shared__ T sU[EPB][NN];  // the element's gathered u, all planes
   __shared__ T sA[EPB][P];
   __shared__ T sB[EPB][P];
@@ -142,18 +171,29 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     g4 = h4;
     g5 = h5;
   }
-  if (!valid) return;
-  const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+  // interior results straight to y, shared ones to the work array; with dpart,
+  // this workgroup's share of u . y over the interior nodes
+  double dacc = 0.0;
+  if (valid) {
+    const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
 #pragma unroll
-  for (int k = 0; k < n1; ++k) {
-    const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
-    int ai, aj, ak;
-    unpack_coef(r.y, ai, aj, ak);
-    const int off = ai * i + aj * j + ak * k;
-    if (r.w & kFlagInterior)
-      y[r.x + off] = (masked_interior && dir[r.x + off]) ? T(0) : rw[k];
-    else
-      w[r.z + off] = rw[k];
+    for (int k = 0; k < n1; ++k) {
+      const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+      int ai, aj, ak;
+      unpack_coef(r.y, ai, aj, ak);
+      const int off = ai * i + aj * j + ak * k;
+      if (r.w & kFlagInterior) {
+        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : rw[k];
+        y[r.x + off] = yv;
+        dacc += (double)sU[le][k * P + ij] * (double)yv;
+      } else {
+        w[r.z + off] = rw[k];
+      }
+    }
+  }
+  if (dpart != nullptr) {
+    const double t = group_sum<EPB * P>(dacc, sRed);
+    if (tid == 0) dpart[blockIdx.x] = t;
   }
 }
 
@@ -173,7 +213,8 @@ typedef double sem_d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256)
 ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* __restrict__ w,
                  const double* __restrict__ G, const int32_t* __restrict__ rec, const double* __restrict__ Dg,
-                 const uint8_t* __restrict__ dir, const int32_t* __restrict__ order, int64_t E) {
+                 const uint8_t* __restrict__ dir, const int32_t* __restrict__ order, int64_t E,
+                 double* __restrict__ dpart) {
   constexpr int N = 15, n1 = 16, P = 256, NN = 4096;
   __shared__ double sU[NN];        // u, later the xi/eta part of the result
   __shared__ double sT[NN];        // zeta derivative of u, later C
@@ -181,7 +222,10 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
   const int64_t pos = xcd_position(blockIdx.x, E);
-  if (pos >= E) return;  // whole workgroup
+  if (pos >= E) {  // whole workgroup
+    if (dpart != nullptr && tid == 0) dpart[blockIdx.x] = 0.0;
+    return;
+  }
   const int64_t e = order[pos];
   // gather: lane tid owns the k-pencil of node (i, j) = (tid % 16, tid / 16)
   {
@@ -262,6 +306,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
   __syncthreads();
   // 3. zeta transpose and output: tile t = row j of every plane
   const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+  double dacc = 0.0;  // share of u . y over interior nodes, with dpart
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int t = wave * 4 + q;
@@ -274,11 +319,19 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
       const int k = 4 * r + lq;
       const double v = acc[r] + sU[k * P + j * n1 + i];
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
-      if (a.flags & kFlagInterior)
-        y[a.g] = (masked_interior && dir[a.g]) ? 0.0 : v;
-      else
+      if (a.flags & kFlagInterior) {
+        const double yv = (masked_interior && dir[a.g]) ? 0.0 : v;
+        y[a.g] = yv;
+        if (dpart != nullptr) dacc += u[a.g] * yv;
+      } else {
         w[a.w] = v;
+      }
     }
+  }
+  if (dpart != nullptr) {
+    __syncthreads();  // sS is reused for the reduction
+    const double tsum = group_sum<256>(dacc, &sS[0][0][0]);
+    if (tid == 0) dpart[blockIdx.x] = tsum;
   }
 }
 
@@ -291,21 +344,31 @@ __global__ void __launch_bounds__(256)
 gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict__ vinc_off,
           const int32_t* __restrict__ einc_off, const uint8_t* __restrict__ fcount,
           const uint8_t* __restrict__ dir, int64_t V, int64_t base_f, int64_t base_i, int m,
-          int64_t wedge_off, int64_t wvert_off) {
+          int64_t wedge_off, int64_t wvert_off, const T* __restrict__ pd, double* __restrict__ dpart) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= base_i) return;
-  T s = 0;
-  if (g < V) {
-    for (int32_t q = vinc_off[g]; q < vinc_off[g + 1]; ++q) s += w[wvert_off + q];
-  } else if (g < base_f) {
-    const int64_t q = g - V, ed = q / m, r = q - ed * m;
-    for (int32_t x = einc_off[ed]; x < einc_off[ed + 1]; ++x) s += w[wedge_off + (int64_t)x * m + r];
-  } else {
-    const int64_t mm = (int64_t)m * m, q = g - base_f, f = q / mm, r = q - f * mm;
-    s = w[2 * f * mm + r];
-    if (fcount[f] == 2) s += w[(2 * f + 1) * mm + r];
+  double d = 0.0;
+  if (g < base_i) {
+    T s = 0;
+    if (g < V) {
+      for (int32_t q = vinc_off[g]; q < vinc_off[g + 1]; ++q) s += w[wvert_off + q];
+    } else if (g < base_f) {
+      const int64_t q = g - V, ed = q / m, r = q - ed * m;
+      for (int32_t x = einc_off[ed]; x < einc_off[ed + 1]; ++x) s += w[wedge_off + (int64_t)x * m + r];
+    } else {
+      const int64_t mm = (int64_t)m * m, q = g - base_f, f = q / mm, r = q - f * mm;
+      s = w[2 * f * mm + r];
+      if (fcount[f] == 2) s += w[(2 * f + 1) * mm + r];
+    }
+    const T yv = dir[g] ? T(0) : s;
+    y[g] = yv;
+    if (dpart != nullptr) d = (double)pd[g] * (double)yv;
   }
-  y[g] = dir[g] ? T(0) : s;
+  // with dpart: this workgroup's share of pd . y over the shared nodes
+  if (dpart != nullptr) {
+    __shared__ double red[256 / 64];
+    const double t = group_sum<256>(d, red);
+    if (threadIdx.x == 0) dpart[blockIdx.x] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -857,6 +920,18 @@ dot_final_kernel(const double* __restrict__ part, double* __restrict__ sc, int n
       sc[0] = s;
     }
   }
+}
+
+// first stage of a reduction over many partial sums: block b sums the
+// partials [b * chunk, (b + 1) * chunk) in a fixed order
+__global__ void __launch_bounds__(kRedThreads)
+sum_chunks_kernel(const double* __restrict__ in, double* __restrict__ out, int64_t n, int64_t chunk) {
+  __shared__ double sh[kRedThreads / 64];
+  const int64_t b0 = (int64_t)blockIdx.x * chunk, b1 = b0 + chunk < n ? b0 + chunk : n;
+  double s = 0.0;
+  for (int64_t x = b0 + threadIdx.x; x < b1; x += blockDim.x) s += in[x];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
 // r -= alpha w; partial sums of r^T r (the matching x update is deferred to
