@@ -145,6 +145,55 @@ def permute_elements(mesh: HexMesh, seed=BASE_SEED + 11) -> tuple[HexMesh, np.nd
                    perm=perm, meta=dict(mesh.meta, permuted=True)), perm
 
 
+def star_mesh(n_sides=5, layers=3, height=1.0, perturb=0.0, seed=BASE_SEED) -> HexMesh:
+    """Extruded polygon whose edges have valence other than 4.
+
+    In the plane: a centre C, spoke points S_i (radius 1, angle 2 pi i/n), mid
+    points M_i (radius 1.25, angle (2i+1) pi/n), and an outer ring T_i, U_i
+    (radii 2.2, 2.4 at the spoke / mid angles).  Quads: kites (C, S_i, S_i+1,
+    M_i) and two outer quads per sector, (S_i, T_i, M_i, U_i) and (M_i, U_i,
+    S_i+1, T_i+1), listed in tensor order with a right-handed frame.  Interior
+    vertices: C (valence n in the plane), S_i (4), M_i (3); extruding into
+    ``layers`` slabs of ``height`` gives interior mesh edges of valence n, 4
+    and 3.  Interior vertices (not on the outer ring, top or bottom) move by
+    uniform draws in (-perturb, +perturb) per coordinate.
+    """
+    n = int(n_sides)
+    ang = 2.0 * np.pi * np.arange(n) / n
+    mid = ang + np.pi / n
+    pts = [(0.0, 0.0)]
+    pts += [(np.cos(a), np.sin(a)) for a in ang]                # S_i: 1 + i
+    pts += [(1.25 * np.cos(a), 1.25 * np.sin(a)) for a in mid]  # M_i: 1 + n + i
+    pts += [(2.2 * np.cos(a), 2.2 * np.sin(a)) for a in ang]    # T_i: 1 + 2n + i
+    pts += [(2.4 * np.cos(a), 2.4 * np.sin(a)) for a in mid]    # U_i: 1 + 3n + i
+    P2 = np.array(pts)
+    S = lambda i: 1 + (i % n)
+    M = lambda i: 1 + n + (i % n)
+    T = lambda i: 1 + 2 * n + (i % n)
+    U = lambda i: 1 + 3 * n + (i % n)
+    quads = []  # tensor order (0,0), (1,0), (0,1), (1,1)
+    for i in range(n):
+        quads.append((0, S(i), S(i + 1), M(i)))
+        quads.append((S(i), T(i), M(i), U(i)))
+        quads.append((M(i), U(i), S(i + 1), T(i + 1)))
+    np2 = P2.shape[0]
+    z = np.linspace(0.0, height, layers + 1)
+    vtx = np.array([(x, y, zz) for zz in z for (x, y) in P2], dtype=np.float64)
+    hexes = []
+    for l in range(layers):
+        for q in quads:
+            hexes.append([l * np2 + v for v in q] + [(l + 1) * np2 + v for v in q])
+    hexes = np.array(hexes, dtype=np.int64)
+    if perturb > 0.0:
+        rng = np.random.default_rng(seed)
+        for v in range(vtx.shape[0]):
+            l, p = divmod(v, np2)
+            if 0 < l < layers and p < 1 + 2 * n:
+                vtx[v] += rng.uniform(-perturb, perturb, size=3)
+    return HexMesh(vtx=vtx, hex=hexes, shape=(n, layers), lengths=(4.8, 4.8, height),
+                   meta=dict(star=n, layers=layers, perturb=perturb))
+
+
 def random_vector(n, seed=BASE_SEED + 3, low=-1.0, high=1.0) -> np.ndarray:
     return np.random.default_rng(seed).uniform(low, high, size=n)
 

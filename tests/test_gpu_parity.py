@@ -35,7 +35,17 @@ CASES = [
     ("rot2_N8", dict(k=(2, 3, 2), perturb=0.1), 8, True),
     ("rot2_N11", dict(k=2, perturb=0.1), 11, True),
     ("one_N15", dict(k=(2, 1, 1), perturb=0.0), 15, True),
+    # extruded polygons: interior mesh edges of valence 3, 4 and 5 (NULL patch slots inside)
+    ("star5_N4", dict(star=5, layers=3, perturb=0.05), 4, True),
+    ("star3_N6", dict(star=3, layers=2, perturb=0.05), 6, True),
 ]
+
+
+def make_mesh(kw):
+    kw = dict(kw)
+    if "star" in kw:
+        return meshgen.star_mesh(kw.pop("star"), **kw)
+    return meshgen.cube_mesh(**kw)
 
 
 @pytest.fixture(scope="module", params=CASES, ids=[c[0] for c in CASES])
@@ -44,7 +54,7 @@ def case(request):
     dev = _dev()
     name, kw, N, rot = request.param
     print(f"[case] {name}", flush=True)
-    m = meshgen.cube_mesh(**kw)
+    m = make_mesh(kw)
     if rot:
         m, _ = meshgen.rotate_elements(m, seed=41)
         m, _ = meshgen.permute_elements(m, seed=42)

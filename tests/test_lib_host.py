@@ -35,13 +35,23 @@ MESHES = [
     ("rot3_N3", dict(k=3, perturb=0.10), 3, True),
     ("rot2_N5", dict(k=2, perturb=0.15), 5, True),
     ("box_N2", dict(k=(3, 2, 4), perturb=0.1, lengths=(1, 1, 8)), 2, True),
+    # extruded polygons: interior mesh edges of valence 3, 4 and 5 (or 3 and 4)
+    ("star5_N4", dict(star=5, layers=3, perturb=0.05), 4, True),
+    ("star3_N3", dict(star=3, layers=2, perturb=0.05), 3, True),
 ]
+
+
+def make_mesh(kw):
+    kw = dict(kw)
+    if "star" in kw:
+        return meshgen.star_mesh(kw.pop("star"), **kw)
+    return meshgen.cube_mesh(**kw)
 
 
 @pytest.fixture(scope="module", params=MESHES, ids=[m[0] for m in MESHES])
 def pair(request):
     name, kw, N, rot = request.param
-    m = meshgen.cube_mesh(**kw)
+    m = make_mesh(kw)
     if rot:
         m, _ = meshgen.rotate_elements(m, seed=31)
         m, _ = meshgen.permute_elements(m, seed=32)
