@@ -32,6 +32,12 @@ constexpr int kGS = 256;
 inline int64_t blocks_for(int64_t n, int t = kGS) { return std::max<int64_t>(1, (n + t - 1) / t); }
 inline int grid_stride_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), 8192); }
 
+// every pointer 16-byte aligned (the streaming kernels then move two entries per access)
+template <typename... P>
+bool aligned16(const P*... ptrs) {
+  return ((reinterpret_cast<uintptr_t>(ptrs) % 16 == 0) && ...);
+}
+
 template <typename T>
 const T* Gp(sem_mesh m);
 template <>
@@ -572,7 +578,8 @@ template <typename TA, typename TB>
 void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s) {
   const int64_t n = m->T.n_global;
   const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
-  hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, s, a, b, m->part.p, n);
+  hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, s, a, b, m->part.p, n,
+                     (int)aligned16(a, b));
   SEM_HIP(hipGetLastError());
   hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dst, mode);
   SEM_HIP(hipGetLastError());
@@ -618,7 +625,7 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   while (status != SEM_OK && k < max_iter) {
     apply_A_dot<T>(m, p, w, 1, 1, s);
     hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)m->sc.p,
-                       m->part.p, n);
+                       m->part.p, n, (int)aligned16(r, w));
     SEM_HIP(hipGetLastError());
     hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 4, 0);
     ++k;
@@ -639,7 +646,8 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
     }
     precond<T>(m, r, z, pc, s);
     dot<T, T>(m, r, z, 5, 2, s);
-    hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)m->sc.p, n);
+    hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)m->sc.p, n,
+                       (int)aligned16(x, p, z));
     SEM_HIP(hipGetLastError());
     pending_x = false;
   }

@@ -878,6 +878,19 @@ __global__ void front_extend_add_kernel(double* __restrict__ F, int64_t f, const
 constexpr int kRedBlocks = 1024;
 constexpr int kRedThreads = 256;
 
+// two consecutive entries as one 16-byte (double) or 8-byte (float) access
+template <typename T>
+struct Pair2;
+template <>
+struct Pair2<double> {
+  typedef double2 type;
+};
+template <>
+struct Pair2<float> {
+  typedef float2 type;
+};
+
+
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -891,11 +904,27 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 template <typename TA, typename TB>
 __global__ void __launch_bounds__(kRedThreads)
-dot_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, double* __restrict__ part, int64_t n) {
+dot_partial_kernel(const TA* __restrict__ a, const TB* __restrict__ b, double* __restrict__ part, int64_t n,
+                   int pairs) {
   __shared__ double sh[kRedThreads / 64];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
-    s += (double)a[x] * (double)b[x];
+  if (pairs) {
+    typedef typename Pair2<TA>::type A2;
+    typedef typename Pair2<TB>::type B2;
+    const A2* a2 = reinterpret_cast<const A2*>(a);
+    const B2* b2 = reinterpret_cast<const B2*>(b);
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n / 2; x += stride) {
+      const A2 av = a2[x];
+      const B2 bv = b2[x];
+      s += (double)av.x * (double)bv.x;
+      s += (double)av.y * (double)bv.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) s += (double)a[n - 1] * (double)b[n - 1];
+  } else {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += stride)
+      s += (double)a[x] * (double)b[x];
+  }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
@@ -936,17 +965,40 @@ sum_chunks_kernel(const double* __restrict__ in, double* __restrict__ out, int64
 
 // r -= alpha w; partial sums of r^T r (the matching x update is deferred to
 // update_px_kernel, which reads p anyway)
+// With `pairs`, entries go two at a time (all pointers 16-byte aligned, a
+// single odd tail entry handled by thread 0 of block 0).
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads)
 update_r_kernel(T* __restrict__ r, const T* __restrict__ w, const double* __restrict__ sc, double* __restrict__ part,
-                int64_t n) {
+                int64_t n, int pairs) {
   __shared__ double sh[kRedThreads / 64];
+  typedef typename Pair2<T>::type T2;
   const T al = (T)sc[2];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double s = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-    const T rn = r[q] - al * w[q];
-    r[q] = rn;
-    s += (double)rn * (double)rn;
+  if (pairs) {
+    T2* r2 = reinterpret_cast<T2*>(r);
+    const T2* w2 = reinterpret_cast<const T2*>(w);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n / 2; q += stride) {
+      const T2 rv = r2[q], wv = w2[q];
+      T2 rn;
+      rn.x = rv.x - al * wv.x;
+      rn.y = rv.y - al * wv.y;
+      r2[q] = rn;
+      s += (double)rn.x * (double)rn.x;
+      s += (double)rn.y * (double)rn.y;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+      const T rn = r[n - 1] - al * w[n - 1];
+      r[n - 1] = rn;
+      s += (double)rn * (double)rn;
+    }
+  } else {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+      const T rn = r[q] - al * w[q];
+      r[q] = rn;
+      s += (double)rn * (double)rn;
+    }
   }
   s = block_sum(s, sh);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -956,13 +1008,36 @@ update_r_kernel(T* __restrict__ r, const T* __restrict__ w, const double* __rest
 template <typename T>
 __global__ void __launch_bounds__(256)
 update_px_kernel(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ sc,
-                 int64_t n) {
+                 int64_t n, int pairs) {
+  typedef typename Pair2<T>::type T2;
   const T al = (T)sc[2];
   const T beta = (T)sc[3];
-  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-    const T pq = p[q];
-    x[q] += al * pq;
-    p[q] = z[q] + beta * pq;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (pairs) {
+    T2* x2 = reinterpret_cast<T2*>(x);
+    T2* p2 = reinterpret_cast<T2*>(p);
+    const T2* z2 = reinterpret_cast<const T2*>(z);
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n / 2; q += stride) {
+      const T2 pq = p2[q], zq = z2[q];
+      T2 xq = x2[q], pn;
+      xq.x += al * pq.x;
+      xq.y += al * pq.y;
+      pn.x = zq.x + beta * pq.x;
+      pn.y = zq.y + beta * pq.y;
+      x2[q] = xq;
+      p2[q] = pn;
+    }
+    if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+      const T pq = p[n - 1];
+      x[n - 1] += al * pq;
+      p[n - 1] = z[n - 1] + beta * pq;
+    }
+  } else {
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+      const T pq = p[q];
+      x[q] += al * pq;
+      p[q] = z[q] + beta * pq;
+    }
   }
 }
 
