@@ -3,7 +3,8 @@
 // Instances of the same order N are concatenated into one disjoint-union mesh:
 // every operator, gather, patch and coarse kernel then covers all of them in
 // one launch (work items = elements of all instances, in the union's Morton
-// order; the coarse levels of the components are merged by level index).  The
+// order; each component is its own tree of the coarse nested dissection, and
+// nodes of all trees at one height share the coarse sweep launches).  The
 // union's canonical numbering restricted to one instance is that instance's
 // own numbering shifted by four offsets (vertices, edges, faces, interiors), so
 // instance vectors map to union vectors by four contiguous copies.

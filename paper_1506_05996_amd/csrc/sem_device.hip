@@ -291,7 +291,7 @@ void release_coarse_graph(sem_mesh m) {
 }
 
 // capture the sweeps once (on a private stream) and replay them on the caller's stream
-void coarse_solve_levels(sem_mesh m, hipStream_t s) {
+void coarse_solve_tree(sem_mesh m, hipStream_t s) {
   if (m->direct_coarse) {
     coarse_sweeps(m, s);
     return;
@@ -349,7 +349,7 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, sc, m->Rlev.p, m->Re.p,
                        m->vinc_off.p, m->vinc_ec.p, m->cidx.p, H.V);
     SEM_HIP(hipGetLastError());
-    coarse_solve_levels(m, sc);
+    coarse_solve_tree(m, sc);
   }
   if (sc != s) {
     SEM_HIP(hipEventRecord(m->ev_join, sc));
@@ -631,8 +631,12 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
     ++k;
     pending_x = true;
     if (k % check_every == 0 || k == max_iter) {
-      rr = read_scalar(m, 4, s);
-      const double flag = read_scalar(m, 6, s);
+      // r^T r (slot 4) and the breakdown flag (slot 6) in one read-back
+      double sc46[3];
+      SEM_HIP(hipMemcpyAsync(sc46, m->sc.p + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
+      SEM_HIP(hipStreamSynchronize(s));
+      rr = sc46[0];
+      const double flag = sc46[2];
       if (st && st->history && st->history_len < st->history_cap)
         st->history[st->history_len++] = std::sqrt(rr / bnorm2);
       if (flag != 0.0 || !std::isfinite(rr)) {
@@ -1061,7 +1065,7 @@ int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask) {
   return guarded([&]() -> int {
     HostTables& T = m->T;
     for (int64_t g = 0; g < T.n_global; ++g) T.dir[g] = mask[g] ? 1 : 0;
-    // the coarse free set follows the vertex nodes: new levels, new factor
+    // the coarse free set follows the vertex nodes: new dissection, new factor
     build_coarse_tree(T);
     update_interior_mask_flags(T);
     if (!m->host_only) {
@@ -1169,7 +1173,7 @@ int sem_coarse_solve(sem_mesh m, const double* R, double* Z, void* stream) {
       hipLaunchKernelGGL(coarse_gather_vertex_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Rlev.p, R,
                          m->cidx.p, T.V);
       SEM_HIP(hipGetLastError());
-      coarse_solve_levels(m, s);
+      coarse_solve_tree(m, s);
     } else {
       hipLaunchKernelGGL((fill_kernel<double>), dim3(grid_stride_blocks(T.V)), dim3(kGS), 0, s, m->Zv.p, 0.0, T.V);
     }

@@ -679,7 +679,7 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
   }
 }
 
-// coarse residual on the free vertices (level order): sum of the element parts
+// coarse residual on the free vertices (coarse order): sum of the element parts
 __global__ void __launch_bounds__(256)
 restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, const int32_t* __restrict__ vinc_off,
                        const int32_t* __restrict__ vinc_ec, const int32_t* __restrict__ cidx, int64_t V) {
