@@ -65,8 +65,8 @@ struct sem_mesh_s {
   DBuf<int32_t> rec, vinc_off, vinc_ec, einc_off, cidx, order;
   DBuf<uint8_t> dir, fcount;
   // operator
-  DBuf<double> G64, D64, w64;
-  DBuf<float> G32, D32, w32;
+  DBuf<double> G64, D64, w64, X864, tq64;  // X8: vertex coordinates, tq: GLL points and weights
+  DBuf<float> G32, D32, w32, X832, tq32;
   // fine preconditioner
   // patch corrections: zo = [zc: E x (N+1)^3 own nodes | zx: E x nx consumer layout]
   DBuf<int32_t> ip, xord, xdest;

@@ -48,6 +48,18 @@ template <typename T>
 const T* Dp(sem_mesh m);
 template <>
 const double* Dp<double>(sem_mesh m) { return m->D64.p; }
+template <typename T>
+const T* X8p(sem_mesh m);
+template <>
+const double* X8p<double>(sem_mesh m) { return m->X864.p; }
+template <>
+const float* X8p<float>(sem_mesh m) { return m->X832.p; }
+template <typename T>
+const T* TQp(sem_mesh m);
+template <>
+const double* TQp<double>(sem_mesh m) { return m->tq64.p; }
+template <>
+const float* TQp<float>(sem_mesh m) { return m->tq32.p; }
 template <>
 const float* Dp<float>(sem_mesh m) { return m->D32.p; }
 template <typename T>
@@ -83,9 +95,11 @@ const float* Hp<float>(sem_mesh m) { return m->h32.p; }
 
 // --- operator ---------------------------------------------------------------
 // tile candidates: elements per workgroup, workgroups of at most 1024 lanes;
-// kTileMfma selects the matrix-core kernel (FP64, N = 15)
+// kTileMfma selects the matrix-core kernel (FP64, N = 15), kTileGeo the kernel
+// that rebuilds the geometric factors from the vertices
 constexpr int kTileCandidates[4] = {1, 2, 4, 8};
 constexpr int kTileMfma = 16;
+constexpr int kTileGeo = 32;  // factors rebuilt from the vertices, default elements per workgroup
 
 template <int N>
 constexpr bool tile_ok(int epb) {
@@ -95,13 +109,14 @@ constexpr bool tile_ok(int epb) {
 // element kernel launches; with dpart, each workgroup also leaves its share
 // of u . y over the element interiors in dpart[block] (the grid size is
 // returned so the caller knows how many)
-template <int N, typename T, int EPB>
+template <int N, typename T, int EPB, bool GEO = false>
 int64_t launch_ax_tile(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   if constexpr (tile_ok<N>(EPB)) {
     const HostTables& T_ = m->T;
     const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((ax_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u, y,
-                       Wp<T>(m), Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart);
+    hipLaunchKernelGGL((ax_kernel<N, T, EPB, GEO>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u,
+                       y, Wp<T>(m), GEO ? X8p<T>(m) : Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart,
+                       TQp<T>(m));
     SEM_HIP(hipGetLastError());
     return grid;
   } else {
@@ -124,6 +139,7 @@ int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
       throw Error{SEM_EINVAL, "the matrix-core operator exists for FP64 at N = 15"};
     }
   }
+  if (epb == kTileGeo) return launch_ax_tile<N, T, ax_epb<N>(), true>(m, u, y, dpart, s);
   switch (epb > 0 ? epb : ax_epb<N>()) {
     case 1: return launch_ax_tile<N, T, 1>(m, u, y, dpart, s);
     case 2: return launch_ax_tile<N, T, 2>(m, u, y, dpart, s);
@@ -522,6 +538,10 @@ void upload_all(sem_mesh m) {
   }
   m->G64.upload(T.G.data(), T.G.size());
   m->D64.upload(T.D.data(), T.D.size());
+  m->X864.upload(T.X8.data(), T.X8.size());
+  std::vector<double> tq(T.t);
+  tq.insert(tq.end(), T.rho.begin(), T.rho.end());
+  m->tq64.upload(tq.data(), tq.size());
   m->w64.alloc(T.w_size);
   m->ip.upload(T.ip.data(), T.ip.size());
   m->xord.upload(T.xord.data(), T.xord.size());
@@ -537,6 +557,10 @@ void upload_all(sem_mesh m) {
     m->G32.upload(G32.data(), G32.size());
     auto D32 = convert<float>(T.D);
     m->D32.upload(D32.data(), D32.size());
+    auto X832 = convert<float>(T.X8);
+    m->X832.upload(X832.data(), X832.size());
+    auto tq32 = convert<float>(tq);
+    m->tq32.upload(tq32.data(), tq32.size());
     m->w32.alloc(T.w_size);
     auto S32 = convert<float>(T.S);
     m->S32.upload(S32.data(), S32.size());
@@ -820,6 +844,7 @@ int tune_tile(sem_mesh m) {
   for (int c : kTileCandidates)
     if (c * (N + 1) * (N + 1) <= 1024 && c * (N + 1) * (N + 1) >= 16) cands.push_back(c);
   if (N == 15 && std::is_same<T, double>::value) cands.push_back(kTileMfma);
+  cands.push_back(kTileGeo);
   if (cands.size() <= 1) return cands.empty() ? 1 : cands[0];
   DBuf<T> u, y;
   u.alloc(m->T.n_global);
@@ -882,7 +907,8 @@ void autotune(sem_mesh m, const char* cache) {
         std::fclose(f);
       }
     }
-    if (found == 1 || found == 2 || found == 4 || found == 8 || (found == kTileMfma && d == 0 && m->T.N == 15)) {
+    if (found == 1 || found == 2 || found == 4 || found == 8 || found == kTileGeo ||
+        (found == kTileMfma && d == 0 && m->T.N == 15)) {
       m->epb[d] = found;
       continue;
     }
@@ -943,8 +969,9 @@ void sem_default_setup_opts(sem_setup_opts* o) {
 int sem_mesh_set_tile(sem_mesh m, int dtype, int epb) {
   if (!m || (dtype != SEM_F64 && dtype != SEM_F32)) return SEM_EINVAL;
   const int N = m->T.N;
-  const bool ok = (epb == 1 || epb == 2 || epb == 4 || epb == 8) ? epb * (N + 1) * (N + 1) <= 1024
-                                                                  : (epb == kTileMfma && N == 15 && dtype == SEM_F64);
+  const bool ok = (epb == 1 || epb == 2 || epb == 4 || epb == 8)
+                      ? epb * (N + 1) * (N + 1) <= 1024
+                      : (epb == kTileGeo || (epb == kTileMfma && N == 15 && dtype == SEM_F64));
   if (!ok) {
     set_error("tile not available for this order and dtype");
     return SEM_EINVAL;

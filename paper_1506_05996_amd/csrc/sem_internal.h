@@ -111,6 +111,7 @@ struct HostTables {
 
   // geometry
   std::vector<double> G;     // [E][6][(N+1)^3]
+  std::vector<double> X8;    // [E][8][3] vertex coordinates in tensor corner order
   std::vector<double> mass;  // [E][(N+1)^3]
   std::vector<double> mN;    // [n_global]
   std::vector<double> xN;    // [n_global][3]

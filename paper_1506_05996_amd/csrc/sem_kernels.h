@@ -93,11 +93,20 @@ __device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nlogical) {
 
 inline int64_t xcd_grid(int64_t nlogical) { return ((nlogical + 7) / 8) * 8; }
 
-template <int N, typename T, int EPB>
-__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1)) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 1, 8)))
+// GEO = false: the factors G are read from memory (6 per node).  GEO = true:
+// they are rebuilt at every node from the element's 8 vertices (Section 3,
+// the variant that trades the factor stream for arithmetic): the columns of
+// the Jacobian of the trilinear map, c0 = dx/dxi etc., their cross products
+// a0 = c1 x c2, a1 = c2 x c0, a2 = c0 x c1 (the rows of det J . J^-1), and
+// G_ab = rho_i rho_j rho_k (a_a . a_b) / det J with det J = c0 . a0, the same
+// rho rho rho |J| (J^T J)^-1 as the stored factors.  In that case G points to
+// the vertex coordinates [E][8][3] and tq to the GLL points and weights [2][N+1].
+template <int N, typename T, int EPB, bool GEO = false>
+__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
+__attribute__((amdgpu_waves_per_eu(N <= 9 ? (GEO && sizeof(T) == 8 ? 3 : 4) : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
           const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
-          const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart) {
+          const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart, const T* __restrict__ tq) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   __shared__ T sD[P];
   __shared__ double sRed[EPB * P];
@@ -117,8 +126,34 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
   const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
   // factors of plane k in registers, plane k+1 prefetched during plane k
-  const T* Ge = G + e * 6 * NN + ij;
-  T g0 = Ge[0 * NN], g1 = Ge[1 * NN], g2 = Ge[2 * NN], g3 = Ge[3 * NN], g4 = Ge[4 * NN], g5 = Ge[5 * NN];
+  const T* Ge = G + (GEO ? e * 24 : e * 6 * NN + ij);
+  T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+  // GEO: the lane's k-independent parts of the Jacobian columns,
+  // c0 = f0(zeta) P0 + f1(zeta) P1, c1 = f0(zeta) Q0 + f1(zeta) Q1, c2 = C2
+  T P0[3], P1[3], Q0[3], Q1[3], C2[3], rij = 0;
+  if constexpr (GEO) {
+    const T ti = tq[i], tj = tq[j];
+    const T f0i = T(0.5) * (T(1) - ti), f1i = T(0.5) * (T(1) + ti);
+    const T f0j = T(0.5) * (T(1) - tj), f1j = T(0.5) * (T(1) + tj);
+    rij = tq[n1 + i] * tq[n1 + j];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      // x(a, b, c) = Ge[(a + 2 b + 4 c) * 3 + q]
+      P0[q] = T(0.5) * ((Ge[1 * 3 + q] - Ge[0 * 3 + q]) * f0j + (Ge[3 * 3 + q] - Ge[2 * 3 + q]) * f1j);
+      P1[q] = T(0.5) * ((Ge[5 * 3 + q] - Ge[4 * 3 + q]) * f0j + (Ge[7 * 3 + q] - Ge[6 * 3 + q]) * f1j);
+      Q0[q] = T(0.5) * ((Ge[2 * 3 + q] - Ge[0 * 3 + q]) * f0i + (Ge[3 * 3 + q] - Ge[1 * 3 + q]) * f1i);
+      Q1[q] = T(0.5) * ((Ge[6 * 3 + q] - Ge[4 * 3 + q]) * f0i + (Ge[7 * 3 + q] - Ge[5 * 3 + q]) * f1i);
+      C2[q] = T(0.5) * ((Ge[4 * 3 + q] - Ge[0 * 3 + q]) * f0i * f0j + (Ge[5 * 3 + q] - Ge[1 * 3 + q]) * f1i * f0j +
+                        (Ge[6 * 3 + q] - Ge[2 * 3 + q]) * f0i * f1j + (Ge[7 * 3 + q] - Ge[3 * 3 + q]) * f1i * f1j);
+    }
+  } else {
+    g0 = Ge[0 * NN];
+    g1 = Ge[1 * NN];
+    g2 = Ge[2 * NN];
+    g3 = Ge[3 * NN];
+    g4 = Ge[4 * NN];
+    g5 = Ge[5 * NN];
+  }
   T rw[n1];
   {
     T uv[n1];
@@ -139,8 +174,36 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   __syncthreads();
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
-    const T* Gn = Ge + (k + 1 < n1 ? k + 1 : 0) * P;
-    const T h0 = Gn[0 * NN], h1 = Gn[1 * NN], h2 = Gn[2 * NN], h3 = Gn[3 * NN], h4 = Gn[4 * NN], h5 = Gn[5 * NN];
+    T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
+    if constexpr (GEO) {
+      const T tk = tq[k];  // wave-uniform
+      const T f0k = T(0.5) * (T(1) - tk), f1k = T(0.5) * (T(1) + tk);
+      T c0[3], c1[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        c0[q] = f0k * P0[q] + f1k * P1[q];
+        c1[q] = f0k * Q0[q] + f1k * Q1[q];
+      }
+      const T a0x = c1[1] * C2[2] - c1[2] * C2[1], a0y = c1[2] * C2[0] - c1[0] * C2[2], a0z = c1[0] * C2[1] - c1[1] * C2[0];
+      const T a1x = C2[1] * c0[2] - C2[2] * c0[1], a1y = C2[2] * c0[0] - C2[0] * c0[2], a1z = C2[0] * c0[1] - C2[1] * c0[0];
+      const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
+      const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
+      const T sc = rij * tq[n1 + k] / det;
+      g0 = sc * (a0x * a0x + a0y * a0y + a0z * a0z);
+      g1 = sc * (a0x * a1x + a0y * a1y + a0z * a1z);
+      g2 = sc * (a0x * a2x + a0y * a2y + a0z * a2z);
+      g3 = sc * (a1x * a1x + a1y * a1y + a1z * a1z);
+      g4 = sc * (a1x * a2x + a1y * a2y + a1z * a2z);
+      g5 = sc * (a2x * a2x + a2y * a2y + a2z * a2z);
+    } else {
+      const T* Gn = Ge + (k + 1 < n1 ? k + 1 : 0) * P;
+      h0 = Gn[0 * NN];
+      h1 = Gn[1 * NN];
+      h2 = Gn[2 * NN];
+      h3 = Gn[3 * NN];
+      h4 = Gn[4 * NN];
+      h5 = Gn[5 * NN];
+    }
     const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
     const T* su = &sU[le][k * P];
     T ur = 0, us = 0, ut = 0;
@@ -164,12 +227,14 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
 #pragma unroll
     for (int m = 0; m < n1; ++m) rw[m] = (m == k) ? rw[m] + acc : rw[m];
     __syncthreads();
-    g0 = h0;
-    g1 = h1;
-    g2 = h2;
-    g3 = h3;
-    g4 = h4;
-    g5 = h5;
+    if constexpr (!GEO) {
+      g0 = h0;
+      g1 = h1;
+      g2 = h2;
+      g3 = h3;
+      g4 = h4;
+      g5 = h5;
+    }
   }
   // interior results straight to y, shared ones to the work array; with dpart,
   // this workgroup's share of u . y over the interior nodes

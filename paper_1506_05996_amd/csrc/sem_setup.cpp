@@ -529,6 +529,7 @@ void build_geometry(HostTables& T, const double* vtx, const int64_t* hex) {
   const int N = T.N, n1 = T.n1;
   const int64_t E = T.E, nn = (int64_t)n1 * n1 * n1;
   T.G.assign((size_t)E * 6 * nn, 0.0);
+  T.X8.assign((size_t)E * 24, 0.0);
   T.mass.assign((size_t)E * nn, 0.0);
   T.h.assign((size_t)E * 3, 0.0);
   std::vector<double> xl((size_t)E * nn * 3);
@@ -539,7 +540,7 @@ void build_geometry(HostTables& T, const double* vtx, const int64_t* hex) {
     for (int64_t e = b0; e < b1; ++e) {
       double X[8][3];
       for (int p = 0; p < 8; ++p)
-        for (int r = 0; r < 3; ++r) X[p][r] = vtx[hex[e * 8 + p] * 3 + r];
+        for (int r = 0; r < 3; ++r) X[p][r] = T.X8[(size_t)e * 24 + p * 3 + r] = vtx[hex[e * 8 + p] * 3 + r];
       // box sizes: mean length of the four edges parallel to each reference axis
       for (int d = 0; d < 3; ++d) {
         double s = 0.0;

@@ -86,6 +86,7 @@ _lib.sem_batch_destroy.argtypes = [_p]
 _lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
 TILE_MFMA = 16
+TILE_GEO = 32  # operator tile that rebuilds the geometric factors from the vertices
 
 
 class SemError(RuntimeError):
