@@ -172,6 +172,18 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     }
   }
   __syncthreads();
+  // FP64 rebuilt-factor form: the lane's two columns of D stay in registers
+  // (fewer LDS reads for the transposed contractions; the other forms keep
+  // their register budget for the factor stream)
+  constexpr bool kDc = GEO && sizeof(T) == 8;
+  T Dci[kDc ? n1 : 1], Dcj[kDc ? n1 : 1];
+  if constexpr (kDc) {
+#pragma unroll
+    for (int m = 0; m < n1; ++m) {
+      Dci[m] = sD[m * n1 + i];
+      Dcj[m] = sD[m * n1 + j];
+    }
+  }
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
     T h0 = 0, h1 = 0, h2 = 0, h3 = 0, h4 = 0, h5 = 0;
@@ -223,7 +235,17 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     __syncthreads();
     T acc = 0;
 #pragma unroll
-    for (int m = 0; m < n1; ++m) acc += sD[m * n1 + i] * sA[le][j * n1 + m] + sD[m * n1 + j] * sB[le][m * n1 + i];
+    for (int m = 0; m < n1; ++m) {
+      T dmi, dmj;
+      if constexpr (kDc) {
+        dmi = Dci[m];
+        dmj = Dcj[m];
+      } else {
+        dmi = sD[m * n1 + i];
+        dmj = sD[m * n1 + j];
+      }
+      acc += dmi * sA[le][j * n1 + m] + dmj * sB[le][m * n1 + i];
+    }
 #pragma unroll
     for (int m = 0; m < n1; ++m) rw[m] = (m == k) ? rw[m] + acc : rw[m];
     __syncthreads();
