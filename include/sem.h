@@ -184,6 +184,36 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
                   sem_solve_stats* st, void* stream);
 
 /*
+ * sem_mesh_set_coefficients -- constant kappa > 0 and c >= 0 of the model
+ * problem c u - div(kappa grad u) = s (eq. (pde)).  Afterwards sem_apply_A
+ * computes kappa times the stiffness action plus c m_N u (the GLL mass is
+ * diagonal, Section 2.4), the patch solves use 1/(4 kappa (lambda_a/h_x^2 +
+ * lambda_b/h_y^2 + lambda_c/h_z^2) + c) (eq. (z)), and the coarse matrix is
+ * the order-1 operator with the same kappa and c (reassembled and
+ * refactorised here; synchronises the device).  Defaults: kappa = 1, c = 0.
+ * Errors: SEM_EINVAL (non-finite, kappa <= 0 or c < 0), SEM_ENOMEM, SEM_EHIP.
+ */
+int sem_mesh_set_coefficients(sem_mesh m, double kappa, double c);
+int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c); /* current values (host out) */
+
+/*
+ * sem_heat_step -- one backward Euler step of the heat equation (Section 6.2):
+ * solves (kappa A + M / dt) u_next = M (u_prev / dt + q) with u = 0 on the
+ * Dirichlet set, where M is the lumped mass m_N.  Sets the coefficients to
+ * (kappa, 1/dt) first (the coarse matrix is refactorised only when they
+ * change), forms the right-hand side on the device, copies u_prev to u_next
+ * and runs sem_pcg_solve from it (o->use_x0 is forced to 1).
+ *   u_prev [n_global] device FP64, the solution at the previous time;
+ *   q      [n_global] device FP64 nodal source at the new time, or NULL (none);
+ *   u_next [n_global] device FP64, out (may be u_prev; must not be q).
+ * Returns what sem_pcg_solve returns; SEM_EINVAL for dt <= 0, kappa <= 0 or
+ * NULL vectors.  Uses an internal right-hand-side buffer of the mesh handle:
+ * calls on one handle must not overlap.
+ */
+int sem_heat_step(sem_mesh m, double kappa, double dt, const double* u_prev_dev, const double* q_dev,
+                  double* u_next_dev, const sem_solve_opts* o, sem_solve_stats* st, void* stream);
+
+/*
  * Batched solves: many independent meshes (of any orders in 2..15) solved
  * together.  Instances of one order share every kernel launch (their meshes
  * are concatenated into one disjoint union), scalars of Algorithm 1 are kept

@@ -214,6 +214,23 @@ def manufactured_s(xyz, lengths=(1.0, 1.0, 1.0)):
     return lam * manufactured_u(xyz, lengths)
 
 
+# Heat-equation workload: the parameters of the aluminium-rod run (kappa in
+# m^2/s, time step in s, a volume source Q over rho c_p) with the source taken
+# as a Gaussian blob that travels along the rod's long (z) axis.
+HEAT = dict(kappa=1e-2, dt=0.04, steps=70, Q=1000.0, rho=7000.0, cp=0.8, sigma=0.2,
+            z_start=0.2, z_end=0.6)
+
+
+def heat_source(xyz, t, lengths, sigma=HEAT["sigma"], amplitude=HEAT["Q"] / (HEAT["rho"] * HEAT["cp"]),
+                z_start=HEAT["z_start"], z_end=HEAT["z_end"], t_end=HEAT["dt"] * HEAT["steps"]):
+    """Nodal source q(x, t): a Gaussian of width sigma centred on the rod axis,
+    its centre moving at constant speed from z_start Lz (t = 0) to z_end Lz (t = t_end)."""
+    Lx, Ly, Lz = lengths
+    zc = Lz * (z_start + (z_end - z_start) * t / t_end)
+    d2 = ((xyz[..., 0] - Lx / 2) ** 2 + (xyz[..., 1] - Ly / 2) ** 2 + (xyz[..., 2] - zc) ** 2)
+    return amplitude * np.exp(-d2 / (2.0 * sigma ** 2))
+
+
 WORKLOADS = {
     # 4^3 hexes of the unit cube, interior vertices +-10% h, order 4 (4913 DOFs)
     "cube4_N4": dict(k=4, lengths=(1.0, 1.0, 1.0), perturb=0.10, N=4, permute=False),
@@ -221,6 +238,9 @@ WORKLOADS = {
     "cube56_N7": dict(k=56, lengths=(1.0, 1.0, 1.0), perturb=0.15, N=7, permute=True),
     # 20^3 hexes stretched 8:1 in z, +-10% h, order 15 (27,270,901 DOFs)
     "box20x8_N15": dict(k=20, lengths=(1.0, 1.0, 8.0), perturb=0.10, N=15, permute=False),
+    # heat-equation rod: 10 x 10 x 625 hexes of a 1 x 1 x 62.5 bar (62,500 hexes,
+    # near the 62,540 of the paper's rod), +-10% h, random ids, order 7 (22,059,416 DOFs)
+    "rod625_N7": dict(k=(10, 10, 625), lengths=(1.0, 1.0, 62.5), perturb=0.10, N=7, permute=True),
 }
 
 

@@ -4,8 +4,9 @@ Test infrastructure.  Steps, in the paper's order and notation:
 
 1. Coarse space: order n = 1 elements on the mesh vertices; the coarse matrix
    A_c is the same spectral-element operator at n = 1 (two-point GLL rule,
-   i.e. quadrature at the 8 corners), assembled on the vertices.  Vertices
-   on the Dirichlet boundary are removed.
+   i.e. quadrature at the 8 corners), assembled on the vertices, with the
+   problem's kappa and c (the c term then lumps to c |J| at each corner).
+   Vertices on the Dirichlet boundary are removed.
 2. Vandermonde B_{IJK,ijk} = Phi_I(t_i) Phi_J(t_j) Phi_K(t_k), 8 x (n+1)^3,
    with Phi_0 = (1 - t)/2, Phi_1 = (1 + t)/2.
 3. Restriction: y_N = r_N / m_N, scattered to y_{ijk;e};
@@ -23,7 +24,8 @@ Library primitives: numpy.einsum, scipy.linalg.cho_factor / cho_solve.
 
 Pinned by: restriction == I^T r and prolongation == I Z for the trilinear
 interpolation matrix I assembled independently node by node; A_c symmetric
-positive definite; A_c equal to the dense order-1 brute-force assembly.
+positive definite; A_c equal to the dense order-1 brute-force assembly, with
+and without kappa and c.
 """
 from __future__ import annotations
 
@@ -50,18 +52,20 @@ def coarse_vertex_ids(num: Numbering) -> np.ndarray:
     return num.l2g[:, ::n, ::n, ::n]
 
 
-def coarse_matrix(vtx, hexes, n_vertices: int) -> scipy.sparse.csr_matrix:
-    """A_c: the order-1 operator on the mesh vertices (sparse, all vertices)."""
+def coarse_matrix(vtx, hexes, n_vertices: int, kappa=1.0, c=0.0) -> scipy.sparse.csr_matrix:
+    """A_c: the order-1 operator kappa K + c M on the mesh vertices (sparse, all vertices)."""
     g1 = GLL(1)
     num1 = number_mesh(hexes, 1)
     geo1 = Geometry(vtx, hexes, g1)
     E = num1.n_elem
+    kap = np.full(E, float(kappa))
+    cc = np.full(E, float(c))
     # element matrices: action on the 8 unit vectors of each element
     K = np.empty((E, 8, 8))
     for col in range(8):
         U = np.zeros((E, 2, 2, 2))
         U.reshape(E, 8)[:, col] = 1.0
-        K[:, :, col] = element_action(U, geo1.G, g1.D).reshape(E, 8)
+        K[:, :, col] = element_action(U, geo1.G, g1.D, kap, cc, geo1.mass).reshape(E, 8)
     idx = num1.l2g.reshape(E, 8)
     rows = np.repeat(idx, 8, axis=1).ravel()
     cols = np.tile(idx, (1, 8)).ravel()
@@ -71,7 +75,7 @@ def coarse_matrix(vtx, hexes, n_vertices: int) -> scipy.sparse.csr_matrix:
 
 class CoarseCorrection:
     def __init__(self, num: Numbering, geo: Geometry, gll: GLL, vtx, hexes, m_global,
-                 dirichlet=None):
+                 dirichlet=None, kappa=1.0, c=0.0):
         self.num = num
         self.geo = geo
         self.B = vandermonde(gll)
@@ -81,7 +85,7 @@ class CoarseCorrection:
         if dirichlet is None:
             dirichlet = num.dirichlet
         self.free = np.nonzero(dirichlet[:nv] == 0)[0]
-        A = coarse_matrix(vtx, hexes, nv)
+        A = coarse_matrix(vtx, hexes, nv, kappa, c)
         self.A_full = A
         self.Ac = A[self.free][:, self.free].toarray()
         self.chol = scipy.linalg.cho_factor(self.Ac, lower=True) if self.free.size else None

@@ -2,7 +2,9 @@
 
 Bundles the steps of Sections 2-4 for a given mesh and order: numbering,
 geometry, lumped mass, node coordinates, operator, two-scale preconditioner
-and PCG.  Nothing here adds arithmetic of its own.
+and PCG, for the model problem c u - div(kappa grad u) = s with constant
+kappa > 0 and c >= 0 (eq. (pde); kappa = 1, c = 0 is the Poisson problem).
+Nothing here adds arithmetic of its own.
 """
 from __future__ import annotations
 
@@ -18,7 +20,7 @@ from .schwarz import FinePreconditioner
 
 
 class Problem:
-    def __init__(self, vtx, hexes, n, fine=True, coarse=True, dirichlet=None):
+    def __init__(self, vtx, hexes, n, fine=True, coarse=True, dirichlet=None, kappa=1.0, c=0.0):
         self.vtx = np.asarray(vtx, dtype=np.float64)
         self.hexes = np.asarray(hexes, dtype=np.int64)
         self.n = n
@@ -28,6 +30,8 @@ class Problem:
         self.m = lumped_mass(self.num, self.geo)
         self.x = node_coords_global(self.num, self.geo)
         self.dirichlet = self.num.dirichlet if dirichlet is None else dirichlet
+        self.kappa = float(kappa)
+        self.c = float(c)
         self._fine_on = fine
         self._coarse_on = coarse
         self._fine = None
@@ -37,18 +41,22 @@ class Problem:
     def fine(self):
         if self._fine is None and self._fine_on:
             self._fine = FinePreconditioner(self.num, self.hexes, self.vtx, self.gll,
-                                            box_sizes(self.vtx, self.hexes))
+                                            box_sizes(self.vtx, self.hexes), self.kappa, self.c)
         return self._fine
 
     @property
     def coarse(self):
         if self._coarse is None and self._coarse_on:
             self._coarse = CoarseCorrection(self.num, self.geo, self.gll, self.vtx, self.hexes,
-                                            self.m, self.dirichlet)
+                                            self.m, self.dirichlet, self.kappa, self.c)
         return self._coarse
 
     def A(self, u):
-        return apply_A(self.num, self.geo, self.gll, u, self.dirichlet)
+        if self.kappa == 1.0 and self.c == 0.0:
+            return apply_A(self.num, self.geo, self.gll, u, self.dirichlet)
+        E = self.num.n_elem
+        return apply_A(self.num, self.geo, self.gll, u, self.dirichlet,
+                       np.full(E, self.kappa), np.full(E, self.c))
 
     def precond(self, fine=True, coarse=True):
         return TwoScale(self.fine if fine else None, self.coarse if coarse else None,
@@ -57,5 +65,5 @@ class Problem:
     def load(self, s_fn):
         return load_vector(self.num, self.m, s_fn(self.x), self.dirichlet)
 
-    def solve(self, b, rtol=1e-8, max_iter=2000, fine=True, coarse=True):
-        return pcg(self.A, b, self.precond(fine, coarse), rtol=rtol, max_iter=max_iter)
+    def solve(self, b, rtol=1e-8, max_iter=2000, fine=True, coarse=True, x0=None):
+        return pcg(self.A, b, self.precond(fine, coarse), rtol=rtol, max_iter=max_iter, x0=x0)

@@ -85,6 +85,10 @@ struct sem_mesh_s {
   hipStream_t side_stream = nullptr;      // coarse chain of the preconditioner, beside the patch solves
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipStream_t capture_stream = nullptr;
+  // lumped mass m_N for the mass term of the operator (uploaded when c != 0),
+  // and the right-hand side of a heat-equation step
+  DBuf<double> mN64, hb;
+  DBuf<float> mN32;
   // PCG work
   DBuf<double> v64[5];
   DBuf<float> v32[5];

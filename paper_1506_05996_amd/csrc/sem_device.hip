@@ -106,6 +106,21 @@ constexpr bool tile_ok(int epb) {
   return epb * (N + 1) * (N + 1) <= 1024;
 }
 
+// coefficients of the operator for dtype T (kappa = 1, c = 0 unless set)
+template <typename T>
+OpCoef<T> op_coef(sem_mesh m) {
+  OpCoef<T> oc;
+  oc.kap = (T)m->T.kappa;
+  oc.cm = (T)m->T.cmass;
+  oc.scaled = (m->T.kappa != 1.0 || m->T.cmass != 0.0) ? 1 : 0;
+  if constexpr (std::is_same<T, double>::value)
+    oc.mN = m->mN64.p;
+  else
+    oc.mN = m->mN32.p;
+  if (m->T.cmass != 0.0 && oc.mN == nullptr) throw Error{SEM_EINVAL, "lumped mass not on the device"};
+  return oc;
+}
+
 // element kernel launches; with dpart, each workgroup also leaves its share
 // of u . y over the element interiors in dpart[block] (the grid size is
 // returned so the caller knows how many)
@@ -116,7 +131,7 @@ int64_t launch_ax_tile(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t 
     const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
     hipLaunchKernelGGL((ax_kernel<N, T, EPB, GEO>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u,
                        y, Wp<T>(m), GEO ? X8p<T>(m) : Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart,
-                       TQp<T>(m));
+                       TQp<T>(m), op_coef<T>(m));
     SEM_HIP(hipGetLastError());
     return grid;
   } else {
@@ -132,7 +147,7 @@ int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
       const HostTables& T_ = m->T;
       const int64_t grid = xcd_grid(T_.E);
       hipLaunchKernelGGL(ax_mfma15_kernel, dim3((unsigned)grid), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
-                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart);
+                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart, op_coef<double>(m));
       SEM_HIP(hipGetLastError());
       return grid;
     } else {
@@ -161,13 +176,18 @@ int default_tile(int N) {
   return 1;
 }
 
+// the shared-node gather; as the operator's last step (u_op = the operator's
+// input) it also applies the coefficients, as the preconditioner's it only sums
 template <typename T>
-int64_t launch_gs(sem_mesh m, T* y, hipStream_t s, const T* pd = nullptr, double* dpart = nullptr) {
+int64_t launch_gs(sem_mesh m, T* y, hipStream_t s, const T* pd = nullptr, double* dpart = nullptr,
+                  const T* u_op = nullptr) {
   const HostTables& T_ = m->T;
   const int64_t grid = blocks_for(T_.base_i);
+  OpCoef<T> oc{T(1), T(0), nullptr, 0};
+  if (u_op != nullptr) oc = op_coef<T>(m);
   hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)grid), dim3(kGS), 0, s, y, Wp<T>(m), m->vinc_off.p,
                      m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1, T_.wedge_off,
-                     T_.wvert_off, pd, dpart);
+                     T_.wvert_off, pd, dpart, oc, u_op);
   SEM_HIP(hipGetLastError());
   return grid;
 }
@@ -190,7 +210,7 @@ int64_t apply_A_elements(sem_mesh m, const T* u, T* y, hipStream_t s, double* dp
 template <typename T>
 void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
   apply_A_elements<T>(m, u, y, s);
-  launch_gs<T>(m, y, s);
+  launch_gs<T>(m, y, s, nullptr, nullptr, u);
 }
 
 // y = A u and u . y into the scalar slot dst (dot_final mode `mode`), the dot
@@ -198,7 +218,7 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
 template <typename T>
 void apply_A_dot(sem_mesh m, const T* u, T* y, int dst, int mode, hipStream_t s) {
   const int64_t na = apply_A_elements<T>(m, u, y, s, m->dpart.p);
-  const int64_t ng = launch_gs<T>(m, y, s, u, m->dpart.p + na);
+  const int64_t ng = launch_gs<T>(m, y, s, u, m->dpart.p + na, u);
   const int64_t n = na + ng;
   const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
   const int nb = (int)((n + chunk - 1) / chunk);
@@ -214,7 +234,8 @@ void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
   T* zc = ZOp<T>(m);
   T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
   hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
-                     m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E);
+                     m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E,
+                     (T)m->T.kappa, (T)m->T.cmass);
   SEM_HIP(hipGetLastError());
 }
 
@@ -688,6 +709,27 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   return status;
 }
 
+// kappa and c of the operator, the patch solves and the coarse matrix (whose
+// values are reassembled and refactorised when they change)
+void set_coefficients(sem_mesh m, double kappa, double c) {
+  HostTables& T = m->T;
+  if (T.kappa == kappa && T.cmass == c) return;
+  T.kappa = kappa;
+  T.cmass = c;
+  assemble_coarse_matrix(T);
+  if (m->host_only) return;
+  SEM_HIP(hipSetDevice(m->device));
+  SEM_HIP(hipDeviceSynchronize());
+  if (c != 0.0 && m->mN64.p == nullptr) {
+    m->mN64.upload(T.mN.data(), T.mN.size());
+    if (m->fp32) {
+      const std::vector<float> f = convert<float>(T.mN);
+      m->mN32.upload(f.data(), f.size());
+    }
+  }
+  factor_coarse(m);
+}
+
 int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, sem_solve_stats* st,
                hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1150,9 +1192,9 @@ int sem_time_apply_A(sem_mesh m, const void* u, void* y, int dtype, int reps, vo
         apply_A_elements<float>(m, (const float*)u, (float*)y, s);
       SEM_HIP(hipEventRecord(ev[3 * r + 1], s));
       if (dtype == SEM_F64)
-        launch_gs<double>(m, (double*)y, s);
+        launch_gs<double>(m, (double*)y, s, nullptr, nullptr, (const double*)u);
       else
-        launch_gs<float>(m, (float*)y, s);
+        launch_gs<float>(m, (float*)y, s, nullptr, nullptr, (const float*)u);
       SEM_HIP(hipEventRecord(ev[3 * r + 2], s));
     }
     SEM_HIP(hipStreamSynchronize(s));
@@ -1221,6 +1263,48 @@ int sem_pcg_solve(sem_mesh m, const double* b, double* x, const sem_solve_opts* 
   return guarded([&]() -> int {
     SEM_HIP(hipSetDevice(m->device));
     return solve_impl(m, b, x, o, st, (hipStream_t)stream);
+  });
+}
+
+int sem_mesh_set_coefficients(sem_mesh m, double kappa, double c) {
+  if (!m || !(kappa > 0.0) || !(c >= 0.0) || !std::isfinite(kappa) || !std::isfinite(c)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    set_coefficients(m, kappa, c);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c) {
+  if (!m || !kappa || !c) return SEM_EINVAL;
+  *kappa = m->T.kappa;
+  *c = m->T.cmass;
+  return SEM_OK;
+}
+
+int sem_heat_step(sem_mesh m, double kappa, double dt, const double* u_prev, const double* q, double* u_next,
+                  const sem_solve_opts* o, sem_solve_stats* st, void* stream) {
+  int s0 = need_device(m);
+  if (s0) return s0;
+  if (!u_prev || !u_next || !(dt > 0.0) || !(kappa > 0.0) || !std::isfinite(dt) || !std::isfinite(kappa))
+    return SEM_EINVAL;
+  if (q == u_next) return SEM_EINVAL;
+  sem_solve_opts d;
+  sem_default_solve_opts(&d);
+  if (!o) o = &d;
+  if (o->pc < 0 || o->pc > 3 || o->max_iter < 0 || !(o->rtol >= 0.0)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    hipStream_t s = (hipStream_t)stream;
+    set_coefficients(m, kappa, 1.0 / dt);
+    const int64_t n = m->T.n_global;
+    if (m->hb.n < (size_t)n) m->hb.alloc(n);
+    hipLaunchKernelGGL(heat_rhs_kernel, dim3((unsigned)blocks_for(n)), dim3(kGS), 0, s, m->hb.p, u_prev, q,
+                       m->mN64.p, m->dir.p, dt, n);
+    SEM_HIP(hipGetLastError());
+    if (u_next != u_prev) SEM_HIP(hipMemcpyAsync(u_next, u_prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    sem_solve_opts oo = *o;
+    oo.use_x0 = 1;
+    return solve_impl(m, m->hb.p, u_next, &oo, st, s);
   });
 }
 

@@ -136,7 +136,12 @@ struct HostTables {
   std::vector<RowItem> fr_items, br_items;  // forward rows (s + b per node), backward columns (s per node)
   std::vector<int64_t> fs_off;            // per height: range of fs_items (small nodes)
   std::vector<RowItem> fs_items;          // 64-row chunks of small nodes' forward rows
-  std::vector<double> corner_K;          // [E][8][8] order-1 element matrices
+  std::vector<double> corner_K;          // [E][8][8] order-1 element stiffness matrices
+  std::vector<double> corner_M;          // [E][8] order-1 element mass (|J| at the corners, diagonal)
+  std::vector<int64_t> coarse_vid;       // [E][8] global id of each element's corner vertices
+
+  // coefficients of the model problem c u - div(kappa grad u) = s (constant)
+  double kappa = 1.0, cmass = 0.0;
 };
 
 // host set-up entry points (sem_setup.cpp)
@@ -146,6 +151,7 @@ void build_geometry(HostTables& T, const double* vtx, const int64_t* hex);
 void build_patches(HostTables& T, const int64_t* hex);
 void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex);
 void build_coarse_tree(HostTables& T, int leaf_max = 0);
+void assemble_coarse_matrix(HostTables& T);
 void export_l2g(const HostTables& T, int32_t* l2g);
 void update_interior_mask_flags(HostTables& T);
 int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k);

@@ -24,6 +24,26 @@ __device__ __forceinline__ void unpack_coef(int32_t code, int& ai, int& aj, int&
 
 __device__ __forceinline__ int node_class(int x, int N) { return x == 0 ? 0 : (x == N ? 2 : 1); }
 
+// Constant coefficients of the model problem c u - div(kappa grad u) = s
+// (eq. (pde)): the operator is kappa times the stiffness action plus c times
+// the mass term.  With GLL quadrature the element mass is diagonal, m_{ijk;e}
+// at each node (Section 2.4), so its assembly is the lumped mass m_N: the
+// kernels add c m_N u_N where each global node's value is written.
+template <typename T>
+struct OpCoef {
+  T kap, cm;
+  const T* mN;  // lumped mass [n_global]; read only when cm != 0
+  int scaled;   // 0 for kappa = 1, c = 0 (the stiffness action alone)
+};
+
+template <typename T>
+__device__ __forceinline__ T op_value(const OpCoef<T>& oc, T stiff, int64_t g, T ug) {
+  if (!oc.scaled) return stiff;
+  T v = oc.kap * stiff;
+  if (oc.cm != T(0)) v += oc.cm * oc.mN[g] * ug;
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Operator kernel, eq. (R) / Algorithm 2.  One (N+1)^2-lane group per element:
 // lane (i,j) keeps the k-pencil of u and of the result in registers, the
@@ -106,7 +126,8 @@ __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
 __attribute__((amdgpu_waves_per_eu(N <= 9 ? (GEO && sizeof(T) == 8 ? 3 : 4) : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
           const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
-          const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart, const T* __restrict__ tq) {
+          const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart, const T* __restrict__ tq,
+          OpCoef<T> oc) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   __shared__ T sD[P];
   __shared__ double sRed[EPB * P];
@@ -270,9 +291,10 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       unpack_coef(r.y, ai, aj, ak);
       const int off = ai * i + aj * j + ak * k;
       if (r.w & kFlagInterior) {
-        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : rw[k];
+        const T uk = sU[le][k * P + ij];
+        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : op_value(oc, rw[k], r.x + off, uk);
         y[r.x + off] = yv;
-        dacc += (double)sU[le][k * P + ij] * (double)yv;
+        dacc += (double)uk * (double)yv;
       } else {
         w[r.z + off] = rw[k];
       }
@@ -301,7 +323,7 @@ __global__ void __launch_bounds__(256)
 ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* __restrict__ w,
                  const double* __restrict__ G, const int32_t* __restrict__ rec, const double* __restrict__ Dg,
                  const uint8_t* __restrict__ dir, const int32_t* __restrict__ order, int64_t E,
-                 double* __restrict__ dpart) {
+                 double* __restrict__ dpart, OpCoef<double> oc) {
   constexpr int N = 15, n1 = 16, P = 256, NN = 4096;
   __shared__ double sU[NN];        // u, later the xi/eta part of the result
   __shared__ double sT[NN];        // zeta derivative of u, later C
@@ -407,9 +429,10 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
       const double v = acc[r] + sU[k * P + j * n1 + i];
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
       if (a.flags & kFlagInterior) {
-        const double yv = (masked_interior && dir[a.g]) ? 0.0 : v;
+        const double ug = (dpart != nullptr || oc.scaled) ? u[a.g] : 0.0;
+        const double yv = (masked_interior && dir[a.g]) ? 0.0 : op_value(oc, v, a.g, ug);
         y[a.g] = yv;
-        if (dpart != nullptr) dacc += u[a.g] * yv;
+        if (dpart != nullptr) dacc += ug * yv;
       } else {
         w[a.w] = v;
       }
@@ -424,14 +447,17 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 
 // ---------------------------------------------------------------------------
 // Gather of the shared nodes (eq. (gather)): one lane per shared global node,
-// copies summed in ascending element order, Dirichlet nodes zeroed.
+// copies summed in ascending element order, Dirichlet nodes zeroed.  As the
+// operator's last step (oc.scaled) it also applies kappa and the mass term at
+// the shared nodes of u; as the preconditioner's assembly it only sums.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
 gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict__ vinc_off,
           const int32_t* __restrict__ einc_off, const uint8_t* __restrict__ fcount,
           const uint8_t* __restrict__ dir, int64_t V, int64_t base_f, int64_t base_i, int m,
-          int64_t wedge_off, int64_t wvert_off, const T* __restrict__ pd, double* __restrict__ dpart) {
+          int64_t wedge_off, int64_t wvert_off, const T* __restrict__ pd, double* __restrict__ dpart,
+          OpCoef<T> oc, const T* __restrict__ u) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d = 0.0;
   if (g < base_i) {
@@ -446,7 +472,7 @@ gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict_
       s = w[2 * f * mm + r];
       if (fcount[f] == 2) s += w[(2 * f + 1) * mm + r];
     }
-    const T yv = dir[g] ? T(0) : s;
+    const T yv = dir[g] ? T(0) : op_value(oc, s, g, oc.scaled ? u[g] : T(0));
     y[g] = yv;
     if (dpart != nullptr) d = (double)pd[g] * (double)yv;
   }
@@ -462,7 +488,8 @@ gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict_
 // Fine patch solve, eq. (z), one workgroup per subdomain.  The (N+3)^3 patch
 // is gathered through I^p into LDS; each of the six 1D contractions is done
 // by lanes that own a whole pencil in registers (one LDS read and one write
-// per node and pass); the diagonal scaling is fused into the zeta pass.  The
+// per node and pass); the diagonal scaling 1/(kappa 4 (lambda_a/h_x^2 +
+// lambda_b/h_y^2 + lambda_c/h_z^2) + c) is fused into the zeta pass.  The
 // correction at the element's own nodes goes to zc; the slots outside the
 // element go to the consumer layout of the element that holds them (zx).
 // ---------------------------------------------------------------------------
@@ -506,7 +533,8 @@ template <int N, typename T>
 __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
            const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
-           const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E) {
+           const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E,
+           T kap, T cm) {
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
   __shared__ T sL[m];
@@ -558,7 +586,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     const T dab = sL[p0] * ihx2 + sL[p1] * ihy2;
     pencil_St<m, T>(S, pen, MM, o);
 #pragma unroll
-    for (int c = 0; c < m; ++c) o[c] = o[c] / (dab + sL[c] * ihz2);
+    for (int c = 0; c < m; ++c) o[c] = o[c] / (kap * (dab + sL[c] * ihz2) + cm);
     pencil_S<m, T>(S, o, pen, MM, T(1));
   }
   __syncthreads();
@@ -1141,6 +1169,16 @@ template <typename TD, typename TS>
 __global__ void __launch_bounds__(256) copy_kernel(TD* __restrict__ d, const TS* __restrict__ s, int64_t n) {
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
     d[q] = (TD)s[q];
+}
+
+// Right-hand side of one backward Euler step of the heat equation (Section
+// 6.2): b_N = m_N (u_N / dt + q_N) on free nodes, 0 on Dirichlet nodes
+// (q = NULL: no source).
+__global__ void __launch_bounds__(256)
+heat_rhs_kernel(double* __restrict__ b, const double* __restrict__ u, const double* __restrict__ q,
+                const double* __restrict__ mN, const uint8_t* __restrict__ dir, double dt, int64_t n) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g < n) b[g] = dir[g] ? 0.0 : mN[g] * (u[g] / dt + (q != nullptr ? q[g] : 0.0));
 }
 
 template <typename T>

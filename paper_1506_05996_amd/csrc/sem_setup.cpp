@@ -891,6 +891,7 @@ void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex)
   const int64_t E = T.E;
   // element matrices of the order-1 operator: quadrature at the 8 corners (weights 1)
   T.corner_K.assign((size_t)E * 64, 0.0);
+  T.corner_M.assign((size_t)E * 8, 0.0);
   parallel_for(E, [&](int64_t b0, int64_t b1) {
     for (int64_t e = b0; e < b1; ++e) {
       double X[8][3];
@@ -908,6 +909,8 @@ void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex)
         double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
                      J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                      J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+        // the mass term with the same corner rule: diagonal, |J| at the corner
+        T.corner_M[e * 8 + q] = det;
         // inverse Jacobian by cofactors: Jinv[a][r]
         double Ji[3][3];
         Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / det;
@@ -1245,7 +1248,15 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
     }
     T.ustack_size = mx;
   }
-  // --- CSR of A_c in coarse order (assembled from the corner matrices, element order)
+  T.coarse_vid = std::move(vid);
+  assemble_coarse_matrix(T);
+}
+
+// CSR of A_c = kappa K_c + c M_c in coarse order, assembled from the corner
+// matrices in element order (the sparsity follows the free vertices)
+void assemble_coarse_matrix(HostTables& T) {
+  const int64_t E = T.E, nc = T.nc;
+  const std::vector<int64_t>& vid = T.coarse_vid;
   std::vector<std::vector<std::pair<int32_t, double>>> rows(nc);
   for (int64_t e = 0; e < E; ++e)
     for (int a = 0; a < 8; ++a) {
@@ -1254,7 +1265,9 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
       for (int b = 0; b < 8; ++b) {
         int32_t cb = T.cidx[vid[e * 8 + b]];
         if (cb < 0) continue;
-        rows[ra].push_back({cb, T.corner_K[e * 64 + a * 8 + b]});
+        double v = T.kappa * T.corner_K[e * 64 + a * 8 + b];
+        if (a == b && T.cmass != 0.0) v += T.cmass * T.corner_M[e * 8 + a];
+        rows[ra].push_back({cb, v});
       }
     }
   T.ac_off.assign(nc + 1, 0);

@@ -36,7 +36,7 @@ EXPORTS = [
     "sem_mesh_node_coords", "sem_mesh_lumped_mass", "sem_mesh_boundary_mask", "sem_mesh_geometry",
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
-    "sem_batch_destroy",
+    "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
 ]
 
 
@@ -84,6 +84,10 @@ _lib.sem_batch_sizes.argtypes = [_p, _p]
 _lib.sem_batch_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), _p, _p]
 _lib.sem_batch_destroy.argtypes = [_p]
 _lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.sem_mesh_set_coefficients.argtypes = [_p, ctypes.c_double, ctypes.c_double]
+_lib.sem_mesh_coefficients.argtypes = [_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.sem_heat_step.argtypes = [_p, ctypes.c_double, ctypes.c_double, _p, _p, _p, ctypes.POINTER(SolveOpts),
+                               ctypes.POINTER(SolveStats), _p]
 _lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
 TILE_MFMA = 16
 TILE_GEO = 32  # operator tile that rebuilds the geometric factors from the vertices
@@ -269,6 +273,43 @@ class Mesh:
             Z = torch.empty_like(R)
         _check(_lib.sem_coarse_solve(self._h, _dptr(R), _dptr(Z), _stream(stream)))
         return Z
+
+    def set_coefficients(self, kappa=1.0, c=0.0):
+        """Constant kappa and c of c u - div(kappa grad u) = s for the operator,
+        the preconditioner and the coarse matrix (refactorised on change)."""
+        _check(_lib.sem_mesh_set_coefficients(self._h, float(kappa), float(c)))
+
+    def coefficients(self):
+        k, c = ctypes.c_double(), ctypes.c_double()
+        _check(_lib.sem_mesh_coefficients(self._h, ctypes.byref(k), ctypes.byref(c)))
+        return k.value, c.value
+
+    def heat_step(self, u_prev, dt, kappa, q=None, u_next=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-10,
+                  max_iter=1000, inner_rtol=3e-3, max_outer=20, check_every=1, stream=None, raise_on_noconv=True):
+        """One backward Euler step of the heat equation: (kappa A + M/dt) u_next =
+        M (u_prev/dt + q), started from u_prev.  Returns (u_next, info)."""
+        import torch
+        self._check_vec(u_prev)
+        if u_prev.dtype != torch.float64:
+            raise TypeError("u_prev must be float64")
+        if q is not None:
+            self._check_vec(q)
+            if q.dtype != torch.float64:
+                raise TypeError("q must be float64")
+        if u_next is None:
+            u_next = torch.empty_like(u_prev)
+        self._check_vec(u_next)
+        opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
+                                  max_outer=max_outer, check_every=check_every, use_x0=1)
+        st = SolveStats()
+        status = _lib.sem_heat_step(self._h, float(kappa), float(dt), _dptr(u_prev),
+                                    _dptr(q) if q is not None else None, _dptr(u_next), ctypes.byref(opts),
+                                    ctypes.byref(st), _stream(stream))
+        info = dict(status=status, iterations=st.iterations, outer=st.outer_iterations,
+                    rel_residual=st.rel_residual, solve_ms=st.solve_ms)
+        if status != SEM_OK and (status != SEM_ENOCONV or raise_on_noconv):
+            raise SemError(status, last_error() + f" ({info})")
+        return u_next, info
 
     def solve(self, b, x=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-8, max_iter=1000, inner_rtol=1e-3,
               max_outer=20, check_every=1, use_x0=False, history=0, stream=None, raise_on_noconv=True):

@@ -122,3 +122,22 @@ def test_host_only_handle_rejects_device_calls():
     lib.sem_apply_A.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int, ctypes.c_void_p]
     st = lib.sem_apply_A(M.handle, ctypes.c_void_p(8), ctypes.c_void_p(16), 0, None)
     assert st == sem.SEM_EUNSUPPORTED
+
+
+def test_coefficients_on_a_host_handle():
+    # kappa and c are validated and stored; the coarse matrix is reassembled on
+    # the host (a host-only handle has no device work to redo)
+    m = meshgen.cube_mesh(2, perturb=0.1)
+    M = sem.Mesh(m.vtx, m.hex, 3, host_only=True)
+    assert M.coefficients() == (1.0, 0.0)
+    M.set_coefficients(0.25, 4.0)
+    assert M.coefficients() == (0.25, 4.0)
+    for kappa, c in ((0.0, 1.0), (-1.0, 0.0), (1.0, -0.5), (float("nan"), 0.0), (1.0, float("inf"))):
+        with pytest.raises(sem.SemError) as e:
+            M.set_coefficients(kappa, c)
+        assert e.value.status == sem.SEM_EINVAL
+    assert M.coefficients() == (0.25, 4.0)
+    lib = ctypes.CDLL(sem.LIB_PATH)
+    lib.sem_heat_step.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 6
+    st = lib.sem_heat_step(M.handle, 1.0, 0.1, ctypes.c_void_p(8), None, ctypes.c_void_p(16), None, None, None)
+    assert st == sem.SEM_EUNSUPPORTED
