@@ -12,7 +12,9 @@ launch stream give the per-kernel durations used for the roofline entry.
 After the timed region, time-to-tolerance of the PCG solve (||b - A x|| /
 ||b|| <= 1e-10, true residual) is measured in plain FP64 and in the
 FP32-refined form: one untimed warm-up solve per form, then the median of
-`--pcg-reps` solves.
+`--pcg-reps` solves.  Then the heat-equation run (Section 6.2) on a
+synthetic rod of 62,500 hexahedra at N = 7: 70 backward Euler steps, each a
+PCG solve to 1e-10, in FP64 and FP32-refined form (`heat` in the output).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -162,6 +164,57 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_heat(args, dev):
+    """The heat-equation run of Section 6.2 on the synthetic rod: 70 backward
+    Euler steps (kappa = 1e-2, dt = 0.04, c = 1/dt, moving source), each a PCG
+    solve to 1e-10 started from the previous step, in FP64 and in the
+    FP32-refined form.  Sources are generated on the device before the timed
+    loop; one untimed step per form first (coefficient set-up, coarse
+    refactorisation, work vectors)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    H = meshgen.HEAT
+    t0 = time.time()
+    mesh, N = meshgen.workload_mesh("rod625_N7")
+    M = sem.Mesh(mesh.vtx, mesh.hex, N)
+    setup_s = time.time() - t0
+    ng = M.n_global
+    x = torch.tensor(M.node_coords(), device=dev)
+    steps, dt, kappa = H["steps"], H["dt"], H["kappa"]
+    qs = [meshgen.heat_source(x, dt * (s + 1), mesh.lengths, exp=torch.exp) for s in range(steps)]
+    del x
+    log(f"[bench] heat: rod {mesh.n_elem} hexes, N={N}, n_global={ng}, setup {setup_s:.1f} s")
+    res = {"workload": "rod625_N7", "hexes": mesh.n_elem, "order": N, "n_global": ng, "steps": steps,
+           "dt": dt, "kappa": kappa, "rtol": 1e-10, "setup_s": round(setup_s, 2)}
+    finals = {}
+    for name, mode in (("fp64", sem.SOLVE_FP64), ("fp32_refined", sem.SOLVE_FP32_REFINED)):
+        kw = dict(mode=mode, rtol=1e-10, max_iter=2000, inner_rtol=args.inner_rtol, max_outer=40)
+        u = torch.zeros(ng, dtype=torch.float64, device=dev)
+        M.heat_step(u, dt, kappa, q=qs[0], **kw)  # warm-up (result discarded)
+        u.zero_()
+        its = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            u, info = M.heat_step(u, dt, kappa, q=qs[s], u_next=u, **kw)
+            its += info["iterations"]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        finals[name] = u
+        res[name] = {"time_s": round(el, 3), "ms_per_step": round(el / steps * 1e3, 2), "iterations": its,
+                     "u_max": float(u.max())}
+        log(f"[bench] heat {name}: {res[name]}")
+    res["speedup_fp32_refined"] = round(res["fp64"]["time_s"] / res["fp32_refined"]["time_s"], 3)
+    d = finals["fp32_refined"] - finals["fp64"]
+    res["fp32_refined_vs_fp64_rel_l2"] = float(torch.linalg.vector_norm(d) / torch.linalg.vector_norm(finals["fp64"]))
+    del qs, finals
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +226,7 @@ def main():
     ap.add_argument("--pcg-reps", type=int, default=3, help="timed solves per mode (median), after one warm-up")
     ap.add_argument("--inner-rtol", type=float, default=3e-3, help="refined form: tolerance of each FP32 inner solve")
     ap.add_argument("--no-serial", action="store_true", help="batch64: skip the one-by-one comparison")
+    ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation run on the rod")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     args = ap.parse_args()
@@ -301,6 +355,11 @@ def main():
         pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
         del b, ue_d, mN
 
+    heat = None
+    if not args.no_heat:
+        del u, y
+        heat = run_heat(args, dev)
+
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU baseline (oracle) ...")
@@ -313,7 +372,7 @@ def main():
            "config": {"workload": args.workload, "hexes": mesh.n_elem, "order": N, "n_global": ng,
                       "perturbation": mesh.meta.get("perturb"), "seed": 1506, "step": "one FP64 apply of A",
                       "setup_s": round(setup_s, 2)},
-           "roofline": roofline, "pcg": pcg, "cpu_baseline": cpu}
+           "roofline": roofline, "pcg": pcg, "heat": heat, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -222,13 +222,14 @@ HEAT = dict(kappa=1e-2, dt=0.04, steps=70, Q=1000.0, rho=7000.0, cp=0.8, sigma=0
 
 
 def heat_source(xyz, t, lengths, sigma=HEAT["sigma"], amplitude=HEAT["Q"] / (HEAT["rho"] * HEAT["cp"]),
-                z_start=HEAT["z_start"], z_end=HEAT["z_end"], t_end=HEAT["dt"] * HEAT["steps"]):
+                z_start=HEAT["z_start"], z_end=HEAT["z_end"], t_end=HEAT["dt"] * HEAT["steps"], exp=np.exp):
     """Nodal source q(x, t): a Gaussian of width sigma centred on the rod axis,
-    its centre moving at constant speed from z_start Lz (t = 0) to z_end Lz (t = t_end)."""
+    its centre moving at constant speed from z_start Lz (t = 0) to z_end Lz (t = t_end).
+    ``exp`` lets array libraries other than numpy evaluate it on their own arrays."""
     Lx, Ly, Lz = lengths
     zc = Lz * (z_start + (z_end - z_start) * t / t_end)
     d2 = ((xyz[..., 0] - Lx / 2) ** 2 + (xyz[..., 1] - Ly / 2) ** 2 + (xyz[..., 2] - zc) ** 2)
-    return amplitude * np.exp(-d2 / (2.0 * sigma ** 2))
+    return amplitude * exp(-d2 / (2.0 * sigma ** 2))
 
 
 WORKLOADS = {
