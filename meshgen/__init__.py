@@ -214,6 +214,39 @@ def manufactured_s(xyz, lengths=(1.0, 1.0, 1.0)):
     return lam * manufactured_u(xyz, lengths)
 
 
+def mixed_bc_u(xyz):
+    """Exact solution sin(pi x) sin(pi y) (z + z^2) on the unit cube: zero on every
+    face but z = 1, where its normal derivative is 3 sin(pi x) sin(pi y)."""
+    return np.sin(np.pi * xyz[..., 0]) * np.sin(np.pi * xyz[..., 1]) * (xyz[..., 2] + xyz[..., 2] ** 2)
+
+
+def mixed_bc_s(xyz):
+    """Source s = -Laplace(u) of :func:`mixed_bc_u` (kappa = 1, c = 0)."""
+    sxy = np.sin(np.pi * xyz[..., 0]) * np.sin(np.pi * xyz[..., 1])
+    z = xyz[..., 2]
+    return sxy * (2.0 * np.pi ** 2 * (z + z ** 2) - 2.0)
+
+
+def mixed_bc_g(xyz):
+    """Neumann data du/dz of :func:`mixed_bc_u` on z = 1."""
+    return 3.0 * np.sin(np.pi * xyz[..., 0]) * np.sin(np.pi * xyz[..., 1])
+
+
+def top_faces(mesh, tol=1e-12):
+    """(element, local face) pairs of the faces lying on z = Lz (local face
+    2 axis + side over the element's tensor corners)."""
+    Lz = mesh.lengths[2]
+    out = []
+    for e, h in enumerate(mesh.hex):
+        X = mesh.vtx[h]  # corner a + 2b + 4c
+        for lf in range(6):
+            d, side = lf // 2, lf % 2
+            corners = [q for q in range(8) if ((q >> d) & 1) == side]
+            if np.all(np.abs(X[corners, 2] - Lz) <= tol):
+                out.append((e, lf))
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
+
+
 # Heat-equation workload: the parameters of the aluminium-rod run (kappa in
 # m^2/s, time step in s, a volume source Q over rho c_p) with the source taken
 # as a Gaussian blob that travels along the rod's long (z) axis.

@@ -53,13 +53,14 @@ def coarse_vertex_ids(num: Numbering) -> np.ndarray:
 
 
 def coarse_matrix(vtx, hexes, n_vertices: int, kappa=1.0, c=0.0) -> scipy.sparse.csr_matrix:
-    """A_c: the order-1 operator kappa K + c M on the mesh vertices (sparse, all vertices)."""
+    """A_c: the order-1 operator kappa K + c M on the mesh vertices (sparse, all
+    vertices); kappa and c are constants or one value per element."""
     g1 = GLL(1)
     num1 = number_mesh(hexes, 1)
     geo1 = Geometry(vtx, hexes, g1)
     E = num1.n_elem
-    kap = np.full(E, float(kappa))
-    cc = np.full(E, float(c))
+    kap = np.broadcast_to(np.asarray(kappa, dtype=np.float64), (E,))
+    cc = np.broadcast_to(np.asarray(c, dtype=np.float64), (E,))
     # element matrices: action on the 8 unit vectors of each element
     K = np.empty((E, 8, 8))
     for col in range(8):

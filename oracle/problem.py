@@ -2,8 +2,9 @@
 
 Bundles the steps of Sections 2-4 for a given mesh and order: numbering,
 geometry, lumped mass, node coordinates, operator, two-scale preconditioner
-and PCG, for the model problem c u - div(kappa grad u) = s with constant
-kappa > 0 and c >= 0 (eq. (pde); kappa = 1, c = 0 is the Poisson problem).
+and PCG, for the model problem c u - div(kappa grad u) = s with kappa > 0 and
+c >= 0 constant or one value per element (eq. (pde), Algorithm 2; kappa = 1,
+c = 0 is the Poisson problem).
 Nothing here adds arithmetic of its own.
 """
 from __future__ import annotations
@@ -30,8 +31,9 @@ class Problem:
         self.m = lumped_mass(self.num, self.geo)
         self.x = node_coords_global(self.num, self.geo)
         self.dirichlet = self.num.dirichlet if dirichlet is None else dirichlet
-        self.kappa = float(kappa)
-        self.c = float(c)
+        E = len(self.hexes)
+        self.kappa = float(kappa) if np.ndim(kappa) == 0 else np.asarray(kappa, dtype=np.float64).reshape(E)
+        self.c = float(c) if np.ndim(c) == 0 else np.asarray(c, dtype=np.float64).reshape(E)
         self._fine_on = fine
         self._coarse_on = coarse
         self._fine = None
@@ -52,11 +54,11 @@ class Problem:
         return self._coarse
 
     def A(self, u):
-        if self.kappa == 1.0 and self.c == 0.0:
+        if np.all(np.asarray(self.kappa) == 1.0) and np.all(np.asarray(self.c) == 0.0):
             return apply_A(self.num, self.geo, self.gll, u, self.dirichlet)
         E = self.num.n_elem
         return apply_A(self.num, self.geo, self.gll, u, self.dirichlet,
-                       np.full(E, self.kappa), np.full(E, self.c))
+                       np.broadcast_to(self.kappa, (E,)), np.broadcast_to(self.c, (E,)))
 
     def precond(self, fine=True, coarse=True):
         return TwoScale(self.fine if fine else None, self.coarse if coarse else None,

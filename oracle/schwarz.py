@@ -231,11 +231,18 @@ def patch_table(num: Numbering, hexes, elements=None) -> np.ndarray:
 
 
 def fdm_patch_solve(S, lam, r_s, h, kappa=1.0, c=0.0):
-    """eq. (z) for patches r_s[s, c, b, a] with box sizes h[s, 3] (step 4)."""
+    """eq. (z) for patches r_s[s, c, b, a] with box sizes h[s, 3] (step 4);
+    kappa and c are constants or one value per patch."""
     t = np.einsum("xa,...cbx->...cba", S, r_s)
     t = np.einsum("xb,...cxa->...cba", S, t)
     t = np.einsum("xc,...xba->...cba", S, t)
     hx, hy, hz = h[..., 0], h[..., 1], h[..., 2]
+    kappa = np.asarray(kappa, dtype=np.float64)
+    c = np.asarray(c, dtype=np.float64)
+    if kappa.ndim:
+        kappa = kappa[:, None, None, None]
+    if c.ndim:
+        c = c[:, None, None, None]
     diag = (4.0 * kappa * (lam[None, None, None, :] / hx[:, None, None, None] ** 2
                            + lam[None, None, :, None] / hy[:, None, None, None] ** 2
                            + lam[None, :, None, None] / hz[:, None, None, None] ** 2)
