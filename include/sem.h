@@ -194,7 +194,36 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
  * Errors: SEM_EINVAL (non-finite, kappa <= 0 or c < 0), SEM_ENOMEM, SEM_EHIP.
  */
 int sem_mesh_set_coefficients(sem_mesh m, double kappa, double c);
-int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c); /* current values (host out) */
+/* Current constant (kappa, c) (host out); NaN while per-element values are in use. */
+int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c);
+
+/*
+ * sem_mesh_set_element_coefficients -- one kappa_e > 0 and c_e >= 0 per
+ * element (host arrays [n_hex] in input element order; NULL: all 1, resp.
+ * all 0), as in Algorithm 2: each element's local values become
+ * kappa_e r_{ijk;e} + c_e m_{ijk;e} u_{ijk;e} before the gather; patch
+ * solve s uses its own element's kappa_e, c_e in eq. (z); the coarse matrix
+ * is assembled with them and refactorised (synchronises the device; uploads
+ * the local mass m_{ijk;e}, [n_hex][(N+1)^3], when some c_e != 0).
+ * sem_mesh_set_coefficients returns the handle to constant coefficients.
+ * Errors: SEM_EINVAL (a value non-finite, kappa_e <= 0 or c_e < 0; nothing
+ * is changed), SEM_ENOMEM, SEM_EHIP.
+ */
+int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa_host, const double* c_host);
+
+/*
+ * sem_mesh_boundary_face_mass -- the Neumann term of eq. (pdeweak): for
+ * du/dn = g on the boundary faces listed, the right-hand side gains
+ * kappa g_N ws_N at each node, where (GLL rule on each face)
+ *   ws_N = sum over the listed faces holding N of rho_p rho_q |dx/da x dx/db|
+ * (a, b the face's two reference axes in increasing order).  faces_host:
+ * [n_faces][2] pairs (element in input order, local face 2 axis + side:
+ * xi-, xi+, eta-, eta+, zeta-, zeta+).  ws_host: [n_global] out (host),
+ * overwritten.  Nodes of Neumann faces must be left out of the Dirichlet set
+ * (sem_mesh_set_dirichlet).  Errors: SEM_EINVAL (NULL, an element or face
+ * index out of range, a face that is not on the boundary).
+ */
+int sem_mesh_boundary_face_mass(sem_mesh m, const int64_t* faces_host, int64_t n_faces, double* ws_host);
 
 /*
  * sem_heat_step -- one backward Euler step of the heat equation (Section 6.2):

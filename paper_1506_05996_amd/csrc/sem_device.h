@@ -89,6 +89,10 @@ struct sem_mesh_s {
   // and the right-hand side of a heat-equation step
   DBuf<double> mN64, hb;
   DBuf<float> mN32;
+  // per-element coefficients kappa_e, c_e [E] and the local mass [E][(N+1)^3]
+  bool per_elem = false, any_ce = false;
+  DBuf<double> ke64, ce64, mL64;
+  DBuf<float> ke32, ce32, mL32;
   // PCG work
   DBuf<double> v64[5];
   DBuf<float> v32[5];

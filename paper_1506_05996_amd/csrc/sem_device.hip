@@ -92,6 +92,18 @@ template <>
 const double* Hp<double>(sem_mesh m) { return m->h64.p; }
 template <>
 const float* Hp<float>(sem_mesh m) { return m->h32.p; }
+template <typename T>
+const T* KEp(sem_mesh m);
+template <>
+const double* KEp<double>(sem_mesh m) { return m->ke64.p; }
+template <>
+const float* KEp<float>(sem_mesh m) { return m->ke32.p; }
+template <typename T>
+const T* CEp(sem_mesh m);
+template <>
+const double* CEp<double>(sem_mesh m) { return m->ce64.p; }
+template <>
+const float* CEp<float>(sem_mesh m) { return m->ce32.p; }
 
 // --- operator ---------------------------------------------------------------
 // tile candidates: elements per workgroup, workgroups of at most 1024 lanes;
@@ -109,7 +121,21 @@ constexpr bool tile_ok(int epb) {
 // coefficients of the operator for dtype T (kappa = 1, c = 0 unless set)
 template <typename T>
 OpCoef<T> op_coef(sem_mesh m) {
-  OpCoef<T> oc;
+  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr};
+  if (m->per_elem) {  // per-element coefficients: applied by the element kernels
+    if constexpr (std::is_same<T, double>::value) {
+      oc.ke = m->ke64.p;
+      oc.ce = m->ce64.p;
+      oc.mL = m->mL64.p;
+    } else {
+      oc.ke = m->ke32.p;
+      oc.ce = m->ce32.p;
+      oc.mL = m->mL32.p;
+    }
+    if (oc.ke == nullptr || oc.ce == nullptr || (m->any_ce && oc.mL == nullptr))
+      throw Error{SEM_EINVAL, "per-element coefficients not on the device"};
+    return oc;
+  }
   oc.kap = (T)m->T.kappa;
   oc.cm = (T)m->T.cmass;
   oc.scaled = (m->T.kappa != 1.0 || m->T.cmass != 0.0) ? 1 : 0;
@@ -183,8 +209,8 @@ int64_t launch_gs(sem_mesh m, T* y, hipStream_t s, const T* pd = nullptr, double
                   const T* u_op = nullptr) {
   const HostTables& T_ = m->T;
   const int64_t grid = blocks_for(T_.base_i);
-  OpCoef<T> oc{T(1), T(0), nullptr, 0};
-  if (u_op != nullptr) oc = op_coef<T>(m);
+  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr};
+  if (u_op != nullptr && !m->per_elem) oc = op_coef<T>(m);
   hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)grid), dim3(kGS), 0, s, y, Wp<T>(m), m->vinc_off.p,
                      m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1, T_.wedge_off,
                      T_.wvert_off, pd, dpart, oc, u_op);
@@ -235,7 +261,8 @@ void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
   T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
   hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
                      m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E,
-                     (T)m->T.kappa, (T)m->T.cmass);
+                     (T)m->T.kappa, (T)m->T.cmass, m->per_elem ? KEp<T>(m) : nullptr,
+                     m->per_elem ? CEp<T>(m) : nullptr);
   SEM_HIP(hipGetLastError());
 }
 
@@ -713,9 +740,12 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
 // values are reassembled and refactorised when they change)
 void set_coefficients(sem_mesh m, double kappa, double c) {
   HostTables& T = m->T;
-  if (T.kappa == kappa && T.cmass == c) return;
+  if (!m->per_elem && T.kappa == kappa && T.cmass == c) return;
   T.kappa = kappa;
   T.cmass = c;
+  T.kap_e.clear();
+  T.c_e.clear();
+  m->per_elem = false;
   assemble_coarse_matrix(T);
   if (m->host_only) return;
   SEM_HIP(hipSetDevice(m->device));
@@ -725,6 +755,45 @@ void set_coefficients(sem_mesh m, double kappa, double c) {
     if (m->fp32) {
       const std::vector<float> f = convert<float>(T.mN);
       m->mN32.upload(f.data(), f.size());
+    }
+  }
+  factor_coarse(m);
+}
+
+// one kappa_e > 0 and c_e >= 0 per element (Algorithm 2): uploaded with the
+// local mass m_{ijk;e} when some c_e != 0; coarse matrix reassembled
+void set_element_coefficients(sem_mesh m, const double* kap, const double* c) {
+  HostTables& T = m->T;
+  const int64_t E = T.E;
+  if (kap)
+    T.kap_e.assign(kap, kap + E);
+  else
+    T.kap_e.assign(E, 1.0);
+  if (c)
+    T.c_e.assign(c, c + E);
+  else
+    T.c_e.assign(E, 0.0);
+  T.kappa = T.cmass = std::nan("");
+  bool any_c = false;
+  for (double v : T.c_e) any_c = any_c || v != 0.0;
+  assemble_coarse_matrix(T);
+  m->per_elem = true;
+  m->any_ce = any_c;
+  if (m->host_only) return;
+  SEM_HIP(hipSetDevice(m->device));
+  SEM_HIP(hipDeviceSynchronize());
+  m->ke64.upload(T.kap_e.data(), E);
+  m->ce64.upload(T.c_e.data(), E);
+  if (m->fp32) {
+    const std::vector<float> kf = convert<float>(T.kap_e), cf = convert<float>(T.c_e);
+    m->ke32.upload(kf.data(), E);
+    m->ce32.upload(cf.data(), E);
+  }
+  if (any_c && m->mL64.p == nullptr) {
+    m->mL64.upload(T.mass.data(), T.mass.size());
+    if (m->fp32) {
+      const std::vector<float> f = convert<float>(T.mass);
+      m->mL32.upload(f.data(), f.size());
     }
   }
   factor_coarse(m);
@@ -1270,6 +1339,27 @@ int sem_mesh_set_coefficients(sem_mesh m, double kappa, double c) {
   if (!m || !(kappa > 0.0) || !(c >= 0.0) || !std::isfinite(kappa) || !std::isfinite(c)) return SEM_EINVAL;
   return guarded([&]() -> int {
     set_coefficients(m, kappa, c);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa, const double* c) {
+  if (!m) return SEM_EINVAL;
+  const int64_t E = m->T.E;
+  for (int64_t e = 0; e < E; ++e) {
+    if (kappa && !(kappa[e] > 0.0 && std::isfinite(kappa[e]))) return SEM_EINVAL;
+    if (c && !(c[e] >= 0.0 && std::isfinite(c[e]))) return SEM_EINVAL;
+  }
+  return guarded([&]() -> int {
+    set_element_coefficients(m, kappa, c);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_boundary_face_mass(sem_mesh m, const int64_t* faces, int64_t n_faces, double* ws) {
+  if (!m || !ws || n_faces < 0 || (n_faces > 0 && !faces)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    boundary_face_mass(m->T, faces, n_faces, ws);
     return SEM_OK;
   });
 }

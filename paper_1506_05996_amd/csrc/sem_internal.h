@@ -140,8 +140,10 @@ struct HostTables {
   std::vector<double> corner_M;          // [E][8] order-1 element mass (|J| at the corners, diagonal)
   std::vector<int64_t> coarse_vid;       // [E][8] global id of each element's corner vertices
 
-  // coefficients of the model problem c u - div(kappa grad u) = s (constant)
+  // coefficients of the model problem c u - div(kappa grad u) = s: constants,
+  // or one value per element (kap_e, c_e non-empty; kappa, cmass are then NaN)
   double kappa = 1.0, cmass = 0.0;
+  std::vector<double> kap_e, c_e;
 };
 
 // host set-up entry points (sem_setup.cpp)
@@ -152,6 +154,7 @@ void build_patches(HostTables& T, const int64_t* hex);
 void build_coarse_matrices(HostTables& T, const double* vtx, const int64_t* hex);
 void build_coarse_tree(HostTables& T, int leaf_max = 0);
 void assemble_coarse_matrix(HostTables& T);
+void boundary_face_mass(const HostTables& T, const int64_t* faces, int64_t n_faces, double* ws);
 void export_l2g(const HostTables& T, int32_t* l2g);
 void update_interior_mask_flags(HostTables& T);
 int64_t gid_of(const HostTables& T, int64_t e, int i, int j, int k);

@@ -29,11 +29,16 @@ __device__ __forceinline__ int node_class(int x, int N) { return x == 0 ? 0 : (x
 // the mass term.  With GLL quadrature the element mass is diagonal, m_{ijk;e}
 // at each node (Section 2.4), so its assembly is the lumped mass m_N: the
 // kernels add c m_N u_N where each global node's value is written.
+// With one kappa_e and c_e per element (Algorithm 2), the element kernel
+// applies them to its own local values instead: kappa_e r + c_e m_{ijk;e} u.
 template <typename T>
 struct OpCoef {
   T kap, cm;
   const T* mN;  // lumped mass [n_global]; read only when cm != 0
-  int scaled;   // 0 for kappa = 1, c = 0 (the stiffness action alone)
+  int scaled;   // constant coefficients other than kappa = 1, c = 0
+  const T* ke;  // per element: kappa_e [E] (NULL: constant coefficients)
+  const T* ce;  // per element: c_e [E]
+  const T* mL;  // per element: local mass m_{ijk;e} [E][(N+1)^3], read where c_e != 0
 };
 
 template <typename T>
@@ -41,6 +46,16 @@ __device__ __forceinline__ T op_value(const OpCoef<T>& oc, T stiff, int64_t g, T
   if (!oc.scaled) return stiff;
   T v = oc.kap * stiff;
   if (oc.cm != T(0)) v += oc.cm * oc.mN[g] * ug;
+  return v;
+}
+
+// local value of element e at local node `loc` with per-element coefficients
+template <typename T>
+__device__ __forceinline__ T elem_value(const OpCoef<T>& oc, int64_t e, int64_t nloc, int loc, T stiff, T ul) {
+  if (oc.ke == nullptr) return stiff;
+  T v = oc.ke[e] * stiff;
+  const T c = oc.ce[e];
+  if (c != T(0)) v += c * oc.mL[e * nloc + loc] * ul;
   return v;
 }
 
@@ -290,13 +305,14 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       int ai, aj, ak;
       unpack_coef(r.y, ai, aj, ak);
       const int off = ai * i + aj * j + ak * k;
+      const T uk = ((r.w & kFlagInterior) || oc.ke != nullptr) ? sU[le][k * P + ij] : T(0);
+      const T v = elem_value(oc, e, NN, k * P + ij, rw[k], uk);
       if (r.w & kFlagInterior) {
-        const T uk = sU[le][k * P + ij];
-        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : op_value(oc, rw[k], r.x + off, uk);
+        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : op_value(oc, v, r.x + off, uk);
         y[r.x + off] = yv;
         dacc += (double)uk * (double)yv;
       } else {
-        w[r.z + off] = rw[k];
+        w[r.z + off] = v;
       }
     }
   }
@@ -426,10 +442,10 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = 4 * r + lq;
-      const double v = acc[r] + sU[k * P + j * n1 + i];
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
+      const double ug = (dpart != nullptr || oc.scaled || oc.ke != nullptr) ? u[a.g] : 0.0;
+      const double v = elem_value(oc, e, NN, k * P + j * n1 + i, acc[r] + sU[k * P + j * n1 + i], ug);
       if (a.flags & kFlagInterior) {
-        const double ug = (dpart != nullptr || oc.scaled) ? u[a.g] : 0.0;
         const double yv = (masked_interior && dir[a.g]) ? 0.0 : op_value(oc, v, a.g, ug);
         y[a.g] = yv;
         if (dpart != nullptr) dacc += ug * yv;
@@ -534,7 +550,7 @@ __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
            const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
            const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E,
-           T kap, T cm) {
+           T kap, T cm, const T* __restrict__ ke, const T* __restrict__ ce) {
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
   __shared__ T X[MMM];
   __shared__ T sL[m];
@@ -561,6 +577,10 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   const T hx = hg[e * 3 + 0], hy = hg[e * 3 + 1], hz = hg[e * 3 + 2];
   const T ihx2 = T(4) / (hx * hx), ihy2 = T(4) / (hy * hy), ihz2 = T(4) / (hz * hz);
   const T vscale = T(8) / (hx * hy * hz);
+  if (ke != nullptr) {  // the subdomain's own element's coefficients
+    kap = ke[e];
+    cm = ce[e];
+  }
   const bool act = tid < MM;
   const int p0 = tid % m, p1 = tid / m;
   T v[m], o[m];

@@ -1252,8 +1252,56 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
   assemble_coarse_matrix(T);
 }
 
+// Lumped surface mass of boundary faces (the Neumann term of eq. (pdeweak)
+// with the GLL rule on each face): ws_N = sum over the listed faces holding
+// node N of rho_p rho_q |dx/da x dx/db|, a and b the face's two reference axes
+// in increasing order, p and q the node's indices along them.  Faces are
+// (element, local face 2 axis + side) pairs and must lie on the boundary.
+void boundary_face_mass(const HostTables& T, const int64_t* faces, int64_t nf, double* ws) {
+  const int N = T.N, n1 = N + 1;
+  for (int64_t f = 0; f < nf; ++f) {
+    const int64_t e = faces[2 * f];
+    const int64_t lf = faces[2 * f + 1];
+    if (e < 0 || e >= T.E || lf < 0 || lf > 5) throw Error{SEM_EINVAL, "face out of range"};
+    if (T.face_nbr[(e * 6 + lf) * 2] >= 0) throw Error{SEM_EINVAL, "Neumann face is not on the boundary"};
+  }
+  std::fill(ws, ws + T.n_global, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    const int64_t e = faces[2 * f];
+    const int d = (int)(faces[2 * f + 1] / 2), side = (int)(faces[2 * f + 1] % 2);
+    const int a = d == 0 ? 1 : 0, b = d == 2 ? 1 : 2;
+    const double* X = &T.X8[e * 24];
+    for (int q = 0; q < n1; ++q)
+      for (int p = 0; p < n1; ++p) {
+        int idx[3];
+        idx[d] = side ? N : 0;
+        idx[a] = p;
+        idx[b] = q;
+        const double x[3] = {T.t[idx[0]], T.t[idx[1]], T.t[idx[2]]};
+        // dx/dxi_r at the node from the trilinear map of the 8 vertices
+        double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int c = 0; c < 8; ++c) {
+          const int bit[3] = {c & 1, (c >> 1) & 1, (c >> 2) & 1};
+          double f[3], df[3];
+          for (int r = 0; r < 3; ++r) {
+            f[r] = bit[r] ? 0.5 * (1.0 + x[r]) : 0.5 * (1.0 - x[r]);
+            df[r] = bit[r] ? 0.5 : -0.5;
+          }
+          const double w[3] = {df[0] * f[1] * f[2], f[0] * df[1] * f[2], f[0] * f[1] * df[2]};
+          for (int r = 0; r < 3; ++r)
+            for (int comp = 0; comp < 3; ++comp) J[comp][r] += X[c * 3 + comp] * w[r];
+        }
+        const double t1[3] = {J[0][a], J[1][a], J[2][a]}, t2[3] = {J[0][b], J[1][b], J[2][b]};
+        const double nx = t1[1] * t2[2] - t1[2] * t2[1], ny = t1[2] * t2[0] - t1[0] * t2[2],
+                     nz = t1[0] * t2[1] - t1[1] * t2[0];
+        ws[gid_of(T, e, idx[0], idx[1], idx[2])] += T.rho[p] * T.rho[q] * std::sqrt(nx * nx + ny * ny + nz * nz);
+      }
+  }
+}
+
 // CSR of A_c = kappa K_c + c M_c in coarse order, assembled from the corner
-// matrices in element order (the sparsity follows the free vertices)
+// matrices in element order with each element's kappa and c (the sparsity
+// follows the free vertices)
 void assemble_coarse_matrix(HostTables& T) {
   const int64_t E = T.E, nc = T.nc;
   const std::vector<int64_t>& vid = T.coarse_vid;
@@ -1265,8 +1313,10 @@ void assemble_coarse_matrix(HostTables& T) {
       for (int b = 0; b < 8; ++b) {
         int32_t cb = T.cidx[vid[e * 8 + b]];
         if (cb < 0) continue;
-        double v = T.kappa * T.corner_K[e * 64 + a * 8 + b];
-        if (a == b && T.cmass != 0.0) v += T.cmass * T.corner_M[e * 8 + a];
+        const double ke = T.kap_e.empty() ? T.kappa : T.kap_e[e];
+        const double ce = T.c_e.empty() ? T.cmass : T.c_e[e];
+        double v = ke * T.corner_K[e * 64 + a * 8 + b];
+        if (a == b && ce != 0.0) v += ce * T.corner_M[e * 8 + a];
         rows[ra].push_back({cb, v});
       }
     }

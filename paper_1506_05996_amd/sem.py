@@ -37,6 +37,7 @@ EXPORTS = [
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
+    "sem_mesh_set_element_coefficients", "sem_mesh_boundary_face_mass",
 ]
 
 
@@ -86,6 +87,8 @@ _lib.sem_batch_destroy.argtypes = [_p]
 _lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.sem_mesh_set_coefficients.argtypes = [_p, ctypes.c_double, ctypes.c_double]
 _lib.sem_mesh_coefficients.argtypes = [_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.sem_mesh_set_element_coefficients.argtypes = [_p, _p, _p]
+_lib.sem_mesh_boundary_face_mass.argtypes = [_p, _p, _i64, _p]
 _lib.sem_heat_step.argtypes = [_p, ctypes.c_double, ctypes.c_double, _p, _p, _p, ctypes.POINTER(SolveOpts),
                                ctypes.POINTER(SolveStats), _p]
 _lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
@@ -278,6 +281,31 @@ class Mesh:
         """Constant kappa and c of c u - div(kappa grad u) = s for the operator,
         the preconditioner and the coarse matrix (refactorised on change)."""
         _check(_lib.sem_mesh_set_coefficients(self._h, float(kappa), float(c)))
+
+    def set_element_coefficients(self, kappa=None, c=None):
+        """One kappa_e and c_e per element (arrays [n_elem], None: 1 resp. 0)."""
+        import numpy as np
+        arrs = []
+        for v in (kappa, c):
+            if v is None:
+                arrs.append(None)
+            else:
+                a = np.ascontiguousarray(v, dtype=np.float64)
+                if a.shape != (self.n_elem,):
+                    raise ValueError(f"expected shape ({self.n_elem},), got {a.shape}")
+                arrs.append(a)
+        _check(_lib.sem_mesh_set_element_coefficients(
+            self._h, *(a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs)))
+
+    def boundary_face_mass(self, faces):
+        """Lumped surface mass ws[n_global] of the listed boundary faces
+        ((element, local face) pairs) for the Neumann term kappa g ws."""
+        import numpy as np
+        f = np.ascontiguousarray(faces, dtype=np.int64).reshape(-1, 2)
+        ws = np.empty(self.n_global, dtype=np.float64)
+        _check(_lib.sem_mesh_boundary_face_mass(self._h, f.ctypes.data_as(ctypes.c_void_p), int(f.shape[0]),
+                                                ws.ctypes.data_as(ctypes.c_void_p)))
+        return ws
 
     def coefficients(self):
         k, c = ctypes.c_double(), ctypes.c_double()

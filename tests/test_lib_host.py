@@ -141,3 +141,51 @@ def test_coefficients_on_a_host_handle():
     lib.sem_heat_step.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double] + [ctypes.c_void_p] * 6
     st = lib.sem_heat_step(M.handle, 1.0, 0.1, ctypes.c_void_p(8), None, ctypes.c_void_p(16), None, None, None)
     assert st == sem.SEM_EUNSUPPORTED
+
+
+def test_boundary_face_mass_matches_oracle():
+    from oracle.gll import GLL
+    from oracle.neumann import face_mass
+    from oracle.numbering import number_mesh
+    m = meshgen.cube_mesh((3, 2, 4), lengths=(1.0, 2.0, 0.5), perturb=0.15, seed=4)
+    m, _ = meshgen.rotate_elements(m, seed=45)
+    faces = meshgen.top_faces(m)
+    for n in (2, 5):
+        M = sem.Mesh(m.vtx, m.hex, n, host_only=True)
+        ws = M.boundary_face_mass(faces)
+        ref = face_mass(number_mesh(m.hex, n), m.vtx, m.hex, GLL(n), faces)
+        assert np.abs(ws - ref).max() <= 1e-14 * ref.max()
+        assert abs(ws.sum() - 2.0) <= 1e-13
+    # interior faces and bad indices are rejected
+    inner = [(e, lf) for e in range(len(m.hex)) for lf in range(6)
+             if not any((e == a and lf == b) for a, b in faces)]
+    M = sem.Mesh(m.vtx, m.hex, 2, host_only=True)
+    n_rejected = 0
+    for f in inner[:40]:
+        try:
+            M.boundary_face_mass([f])
+        except sem.SemError as e:
+            assert e.status == sem.SEM_EINVAL
+            n_rejected += 1
+    assert n_rejected > 0
+    for bad in ([(len(m.hex), 0)], [(0, 6)], [(-1, 0)]):
+        with pytest.raises(sem.SemError):
+            M.boundary_face_mass(bad)
+
+
+def test_element_coefficients_validation_on_a_host_handle():
+    m = meshgen.cube_mesh(2, perturb=0.1)
+    M = sem.Mesh(m.vtx, m.hex, 3, host_only=True)
+    E = len(m.hex)
+    M.set_element_coefficients(np.full(E, 0.5), np.full(E, 2.0))
+    k, c = M.coefficients()
+    assert np.isnan(k) and np.isnan(c)
+    bad = np.full(E, 0.5)
+    bad[3] = -1.0
+    with pytest.raises(sem.SemError) as e:
+        M.set_element_coefficients(bad, None)
+    assert e.value.status == sem.SEM_EINVAL
+    with pytest.raises(ValueError):
+        M.set_element_coefficients(np.ones(E + 1), None)
+    M.set_coefficients(1.0, 0.0)
+    assert M.coefficients() == (1.0, 0.0)
