@@ -191,8 +191,8 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     g5 = Ge[5 * NN];
   }
   T rw[n1];
+  T uv[n1];  // the lane's own pencil of u (GEO: also used for the zeta derivative)
   {
-    T uv[n1];
 #pragma unroll
     for (int k = 0; k < n1; ++k) {
       const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
@@ -259,7 +259,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
     for (int m = 0; m < n1; ++m) {
       ur += sD[i * n1 + m] * su[j * n1 + m];
       us += sD[j * n1 + m] * su[m * n1 + i];
-      ut += Dk[m] * sU[le][m * P + ij];
+      ut += Dk[m] * (GEO ? uv[m] : sU[le][m * P + ij]);
     }
     const T A = g0 * ur + g1 * us + g2 * ut;
     const T B = g1 * ur + g3 * us + g4 * ut;
