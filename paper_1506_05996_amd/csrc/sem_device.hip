@@ -268,22 +268,28 @@ void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
 
 // element-wise sum of the corrections (+ coarse interpolation) into z and w
 template <int N, typename T>
-void launch_schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s) {
+int64_t launch_schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s, const T* rd,
+                           double* dpart) {
   constexpr int EPB = ax_epb<N>();
   const T* zc = ZOp<T>(m);
   const T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
   const int64_t grid = xcd_grid((m->T.E + EPB - 1) / EPB);
   hipLaunchKernelGGL((schwarz_sum_kernel<N, T, EPB>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, z,
-                     Wp<T>(m), zc, zx, m->rec.p, m->dir.p, m->order.p, m->T.E, (int)fine, Zv, m->phi.p);
+                     Wp<T>(m), zc, zx, m->rec.p, m->dir.p, m->order.p, m->T.E, (int)fine, Zv, m->phi.p, rd, dpart);
   SEM_HIP(hipGetLastError());
+  return grid;
 }
 
+// the preconditioner's result from the patch corrections and the coarse
+// interpolation; with dpart, also the partial sums of rd . z (returns their count)
 template <typename T>
-void schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s) {
+int64_t schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s, const T* rd = nullptr,
+                    double* dpart = nullptr) {
+  int64_t na = 0;
   switch (m->T.N) {
-#define CASE(NN)                                        \
-  case NN:                                              \
-    launch_schwarz_sum<NN, T>(m, z, fine, Zv, s);       \
+#define CASE(NN)                                                     \
+  case NN:                                                           \
+    na = launch_schwarz_sum<NN, T>(m, z, fine, Zv, s, rd, dpart);    \
     break;
     CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
     CASE(15)
@@ -291,7 +297,8 @@ void schwarz_sum(sem_mesh m, T* z, bool fine, const double* Zv, hipStream_t s) {
     default:
       throw Error{SEM_EUNSUPPORTED, "order not compiled"};
   }
-  launch_gs<T>(m, z, s);
+  const int64_t ng = launch_gs<T>(m, z, s, rd, dpart != nullptr ? dpart + na : nullptr);
+  return na + ng;
 }
 
 template <int N, typename T>
@@ -383,12 +390,26 @@ void coarse_solve_tree(sem_mesh m, hipStream_t s) {
 }
 
 template <typename T>
+void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s);
+
+template <typename T>
 void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
+  precond_dot<T>(m, r, z, pc, -1, 0, s);
+}
+
+template <typename TA, typename TB>
+void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s);
+
+// z = P r; with dot_dst >= 0 also r . z into scalar slot dot_dst (dot_final
+// mode dot_mode), taken from the preconditioner's own output kernels
+template <typename T>
+void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s) {
   const HostTables& H = m->T;
   const bool fine = pc & SEM_PC_FINE, coarse = (pc & SEM_PC_COARSE) && H.nc > 0;
   if (pc == SEM_PC_NONE) {
     hipLaunchKernelGGL((copy_kernel<T, T>), dim3(grid_stride_blocks(H.n_global)), dim3(kGS), 0, s, z, r, H.n_global);
     SEM_HIP(hipGetLastError());
+    if (dot_dst >= 0) dot<T, T>(m, r, z, dot_dst, dot_mode, s);
     return;
   }
   // The coarse and fine parts are independent until the final sum: the
@@ -419,7 +440,17 @@ void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
     SEM_HIP(hipEventRecord(m->ev_join, sc));
     SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
   }
-  schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s);
+  if (dot_dst < 0) {
+    schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s);
+    return;
+  }
+  const int64_t n = schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s, r, m->dpart.p);
+  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const int nb = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->dpart.p, m->part.p, n,
+                     chunk);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dot_dst, dot_mode);
+  SEM_HIP(hipGetLastError());
 }
 
 // --- coarse factorisation (set-up), multifrontal in post-order.  Node t's
@@ -685,9 +716,8 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
   const int gb = grid_stride_blocks(n);
   hipLaunchKernelGGL((fill_kernel<double>), dim3(1), dim3(kGS), 0, s, m->sc.p, 0.0, (int64_t)7);
-  precond<T>(m, r, z, pc, s);
+  precond_dot<T>(m, r, z, pc, 0, 0, s);
   hipLaunchKernelGGL((copy_kernel<T, T>), dim3(gb), dim3(kGS), 0, s, p, z, n);
-  dot<T, T>(m, r, z, 0, 0, s);
   const double tol2 = rtol * rtol * bnorm2;
   int k = 0;
   double rr = bnorm2;
@@ -720,8 +750,7 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
         break;
       }
     }
-    precond<T>(m, r, z, pc, s);
-    dot<T, T>(m, r, z, 5, 2, s);
+    precond_dot<T>(m, r, z, pc, 5, 2, s);
     hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)m->sc.p, n,
                        (int)aligned16(x, p, z));
     SEM_HIP(hipGetLastError());

@@ -136,6 +136,19 @@ inline int64_t xcd_grid(int64_t nlogical) { return ((nlogical + 7) / 8) * 8; }
 // G_ab = rho_i rho_j rho_k (a_a . a_b) / det J with det J = c0 . a0, the same
 // rho rho rho |J| (J^T J)^-1 as the stored factors.  In that case G points to
 // the vertex coordinates [E][8][3] and tq to the GLL points and weights [2][N+1].
+// 1/d for a positive, normal d: hardware reciprocal refined by Newton steps
+// (two in FP64, one in FP32): within about an ulp of the rounded quotient
+__device__ __forceinline__ double recip_pos(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+  y = __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+  return __builtin_fma(y, __builtin_fma(-d, y, 1.0), y);
+}
+
+__device__ __forceinline__ float recip_pos(float d) {
+  const float y = __builtin_amdgcn_rcpf(d);
+  return __builtin_fmaf(y, __builtin_fmaf(-d, y, 1.0f), y);
+}
+
 template <int N, typename T, int EPB, bool GEO = false>
 __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
 __attribute__((amdgpu_waves_per_eu(N <= 9 ? (GEO && sizeof(T) == 8 ? 3 : 4) : 1, 8)))
@@ -236,7 +249,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       const T a1x = C2[1] * c0[2] - C2[2] * c0[1], a1y = C2[2] * c0[0] - C2[0] * c0[2], a1z = C2[0] * c0[1] - C2[1] * c0[0];
       const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
       const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
-      const T sc = rij * tq[n1 + k] / det;
+      const T sc = rij * tq[n1 + k] * recip_pos(det);
       g0 = sc * (a0x * a0x + a0y * a0y + a0z * a0z);
       g1 = sc * (a0x * a1x + a0y * a1y + a0z * a1z);
       g2 = sc * (a0x * a2x + a0y * a2y + a0z * a2z);
@@ -656,20 +669,24 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
 // neighbouring patches left in e's consumer layout (zx: planes one layer in
 // from each face, lines one layer in from both faces of each edge, corner
 // points), then I Z at the nodes e owns.  Element interiors go straight to z
-// (Dirichlet zeroed), shared nodes to the work array for gs_kernel.
+// (Dirichlet zeroed), shared nodes to the work array for gs_kernel.  With
+// dpart, each workgroup also leaves its share of rd . z over the interior
+// nodes (the gather adds the shared nodes' share), so that PCG's r . z needs
+// no pass of its own.
 // ---------------------------------------------------------------------------
 template <int N, typename T, int EPB>
 __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
 schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ zc, const T* __restrict__ zx,
                    const int32_t* __restrict__ rec, const uint8_t* __restrict__ dir,
                    const int32_t* __restrict__ order, int64_t E, int use_fine, const double* __restrict__ Zv,
-                   const double* __restrict__ phi) {
+                   const double* __restrict__ phi, const T* __restrict__ rd, double* __restrict__ dpart) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   constexpr int NX = (N + 3) * (N + 3) * (N + 3) - NN;
   constexpr int F0 = 0, E0 = 6 * P, C0 = 6 * P + 12 * n1;
   constexpr int RX = (NX + P - 1) / P;
   __shared__ T sX[EPB][NX];  // the element's consumer layout, staged with coalesced loads
   __shared__ double sPhi[2 * n1];
+  __shared__ double sRed[EPB * P];
   const int tid = threadIdx.x;
   const int le = tid / P, ij = tid - le * P;
   const int i = ij % n1, j = ij / n1;
@@ -703,11 +720,12 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
     for (int x = tid; x < 2 * n1; x += EPB * P) sPhi[x] = phi[x];
   }
   __syncthreads();
-  if (!valid) return;
   const T* xs = sX[le];
   const bool li0 = i == 1, li1 = i == N - 1, lj0 = j == 1, lj1 = j == N - 1;
+  double dacc = 0.0;  // with dpart: this workgroup's share of rd . z over the interior nodes
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
+    if (!valid) break;
     const bool lk0 = k == 1, lk1 = k == N - 1;
     T v = 0;
     if (use_fine) {
@@ -748,10 +766,17 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
     int ai, aj, ak;
     unpack_coef(rr.y, ai, aj, ak);
     const int off = ai * i + aj * j + ak * k;
-    if (rr.w & kFlagInterior)
-      z[rr.x + off] = (masked_interior && dir[rr.x + off]) ? T(0) : v;
-    else
+    if (rr.w & kFlagInterior) {
+      const T zv = (masked_interior && dir[rr.x + off]) ? T(0) : v;
+      z[rr.x + off] = zv;
+      if (dpart != nullptr) dacc += (double)rd[rr.x + off] * (double)zv;
+    } else {
       w[rr.z + off] = v;
+    }
+  }
+  if (dpart != nullptr) {
+    const double t = group_sum<EPB * P>(dacc, sRed);
+    if (tid == 0) dpart[blockIdx.x] = t;
   }
 }
 
