@@ -12,7 +12,8 @@ launch stream give the per-kernel durations used for the roofline entry.
 After the timed region, time-to-tolerance of the PCG solve (||b - A x|| /
 ||b|| <= 1e-10, true residual) is measured in plain FP64 and in the
 FP32-refined form: one untimed warm-up solve per form, then the median of
-`--pcg-reps` solves.  Then the heat-equation run (Section 6.2) on a
+`--pcg-reps` solves.  Then a solve with one kappa per element and a Neumann
+face (`coefficients`), and the heat-equation run (Section 6.2) on a
 synthetic rod of 62,500 hexahedra at N = 7: 70 backward Euler steps, each a
 PCG solve to 1e-10, in FP64 and FP32-refined form (`heat` in the output).
 
@@ -164,6 +165,59 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_coefficients(M, mesh, dev, args):
+    """Per-element coefficients and Neumann data on the same mesh: kappa_e
+    log-uniform in [0.1, 10] (seed 1507; 1 on the elements with a face on
+    z = Lz), c_e = 0, Dirichlet on every face but z = Lz, Neumann g = 1 there,
+    source s = 1.  The operator timed, then PCG to 1e-10 in FP64 and
+    FP32-refined form (one warm-up solve each)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    faces = meshgen.top_faces(mesh)
+    kap = 10.0 ** np.random.default_rng(1507).uniform(-1.0, 1.0, mesh.n_elem)
+    kap[faces[:, 0]] = 1.0
+    t0 = time.time()
+    M.set_element_coefficients(kap, None)
+    x = M.node_coords()
+    Lx, Ly, Lz = mesh.lengths
+    top = np.abs(x[:, 2] - Lz) <= 1e-12
+    side = ((np.abs(x[:, 0]) <= 1e-12) | (np.abs(x[:, 0] - Lx) <= 1e-12)
+            | (np.abs(x[:, 1]) <= 1e-12) | (np.abs(x[:, 1] - Ly) <= 1e-12))
+    dirichlet = (M.boundary_mask().astype(bool) & ~(top & ~side)).astype(np.uint8)
+    del x, top, side
+    M.set_dirichlet(dirichlet)
+    b = M.lumped_mass() + M.boundary_face_mass(faces)  # s = 1, kappa g = 1 on the Neumann faces
+    b[dirichlet.astype(bool)] = 0.0
+    setup = time.time() - t0
+    bd = torch.tensor(b, device=dev)
+    del b, dirichlet
+    u = torch.tensor(np.random.default_rng(1506).uniform(-1, 1, M.n_global), device=dev)
+    y = torch.empty_like(u)
+    for _ in range(3):
+        M.apply_A(u, y)
+    te, tg = M.time_apply_A(u, y, 20)
+    del u, y
+    res = {"kappa": "per element, log-uniform in [0.1, 10]", "neumann_faces": int(len(faces)),
+           "setup_s": round(setup, 2), "ms_ax_kernel": round(te, 4), "ms_gs_kernel": round(tg, 4)}
+    for name, mode in (("fp64", sem.SOLVE_FP64), ("fp32_refined", sem.SOLVE_FP32_REFINED)):
+        kw = dict(mode=mode, rtol=1e-10, max_iter=4000, inner_rtol=args.inner_rtol, max_outer=40)
+        M.solve(bd, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, info = M.solve(bd, **kw)
+        torch.cuda.synchronize()
+        r = bd - M.apply_A(xs)
+        res[name] = {"time_s": round(time.perf_counter() - t0, 4), "iterations": info["iterations"],
+                     "outer": info["outer"],
+                     "true_rel_residual": float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(bd))}
+        log(f"[bench] coefficients {name}: {res[name]}")
+    return res
+
+
 def run_heat(args, dev):
     """The heat-equation run of Section 6.2 on the synthetic rod: 70 backward
     Euler steps (kappa = 1e-2, dt = 0.04, c = 1/dt, moving source), each a PCG
@@ -227,6 +281,8 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=3e-3, help="refined form: tolerance of each FP32 inner solve")
     ap.add_argument("--no-serial", action="store_true", help="batch64: skip the one-by-one comparison")
     ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation run on the rod")
+    ap.add_argument("--no-coef", action="store_true",
+                    help="skip the per-element-coefficient / Neumann solve on the main mesh")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     args = ap.parse_args()
@@ -355,6 +411,10 @@ def main():
         pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
         del b, ue_d, mN
 
+    coefs = None
+    if not args.no_coef:
+        coefs = run_coefficients(M, mesh, dev, args)
+
     heat = None
     if not args.no_heat:
         del u, y
@@ -372,7 +432,7 @@ def main():
            "config": {"workload": args.workload, "hexes": mesh.n_elem, "order": N, "n_global": ng,
                       "perturbation": mesh.meta.get("perturb"), "seed": 1506, "step": "one FP64 apply of A",
                       "setup_s": round(setup_s, 2)},
-           "roofline": roofline, "pcg": pcg, "heat": heat, "cpu_baseline": cpu}
+           "roofline": roofline, "pcg": pcg, "coefficients": coefs, "heat": heat, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -236,14 +236,15 @@ def top_faces(mesh, tol=1e-12):
     """(element, local face) pairs of the faces lying on z = Lz (local face
     2 axis + side over the element's tensor corners)."""
     Lz = mesh.lengths[2]
+    Z = mesh.vtx[mesh.hex][..., 2]  # [E, 8], corner a + 2b + 4c
+    on_top = np.abs(Z - Lz) <= tol
     out = []
-    for e, h in enumerate(mesh.hex):
-        X = mesh.vtx[h]  # corner a + 2b + 4c
-        for lf in range(6):
-            d, side = lf // 2, lf % 2
-            corners = [q for q in range(8) if ((q >> d) & 1) == side]
-            if np.all(np.abs(X[corners, 2] - Lz) <= tol):
-                out.append((e, lf))
+    for lf in range(6):
+        d, side = lf // 2, lf % 2
+        corners = [q for q in range(8) if ((q >> d) & 1) == side]
+        for e in np.nonzero(on_top[:, corners].all(axis=1))[0]:
+            out.append((int(e), lf))
+    out.sort()
     return np.array(out, dtype=np.int64).reshape(-1, 2)
 
 
