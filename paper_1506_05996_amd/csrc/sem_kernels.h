@@ -49,13 +49,26 @@ __device__ __forceinline__ T op_value(const OpCoef<T>& oc, T stiff, int64_t g, T
   return v;
 }
 
+// element e's kappa_e, c_e (1, 0 without per-element coefficients), read
+// once per element before its results are stored
+template <typename T>
+struct ElemCoef {
+  T k, c;
+};
+
+template <typename T>
+__device__ __forceinline__ ElemCoef<T> elem_coef(const OpCoef<T>& oc, int64_t e) {
+  if (oc.ke == nullptr) return ElemCoef<T>{T(1), T(0)};
+  return ElemCoef<T>{oc.ke[e], oc.ce[e]};
+}
+
 // local value of element e at local node `loc` with per-element coefficients
 template <typename T>
-__device__ __forceinline__ T elem_value(const OpCoef<T>& oc, int64_t e, int64_t nloc, int loc, T stiff, T ul) {
+__device__ __forceinline__ T elem_value(const OpCoef<T>& oc, const ElemCoef<T>& ec, int64_t e, int64_t nloc, int loc,
+                                        T stiff, T ul) {
   if (oc.ke == nullptr) return stiff;
-  T v = oc.ke[e] * stiff;
-  const T c = oc.ce[e];
-  if (c != T(0)) v += c * oc.mL[e * nloc + loc] * ul;
+  T v = ec.k * stiff;
+  if (ec.c != T(0)) v += ec.c * oc.mL[e * nloc + loc] * ul;
   return v;
 }
 
@@ -312,6 +325,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   double dacc = 0.0;
   if (valid) {
     const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+    const ElemCoef<T> ec = elem_coef(oc, e);
 #pragma unroll
     for (int k = 0; k < n1; ++k) {
       const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
@@ -319,7 +333,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       unpack_coef(r.y, ai, aj, ak);
       const int off = ai * i + aj * j + ak * k;
       const T uk = ((r.w & kFlagInterior) || oc.ke != nullptr) ? sU[le][k * P + ij] : T(0);
-      const T v = elem_value(oc, e, NN, k * P + ij, rw[k], uk);
+      const T v = elem_value(oc, ec, e, NN, k * P + ij, rw[k], uk);
       if (r.w & kFlagInterior) {
         const T yv = (masked_interior && dir[r.x + off]) ? T(0) : op_value(oc, v, r.x + off, uk);
         y[r.x + off] = yv;
@@ -444,6 +458,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
   __syncthreads();
   // 3. zeta transpose and output: tile t = row j of every plane
   const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+  const ElemCoef<double> ec = elem_coef(oc, e);
   double dacc = 0.0;  // share of u . y over interior nodes, with dpart
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -457,7 +472,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
       const int k = 4 * r + lq;
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
       const double ug = (dpart != nullptr || oc.scaled || oc.ke != nullptr) ? u[a.g] : 0.0;
-      const double v = elem_value(oc, e, NN, k * P + j * n1 + i, acc[r] + sU[k * P + j * n1 + i], ug);
+      const double v = elem_value(oc, ec, e, NN, k * P + j * n1 + i, acc[r] + sU[k * P + j * n1 + i], ug);
       if (a.flags & kFlagInterior) {
         const double yv = (masked_interior && dir[a.g]) ? 0.0 : op_value(oc, v, a.g, ug);
         y[a.g] = yv;
