@@ -14,7 +14,8 @@ Test infrastructure.  Steps, in the paper's order and notation:
    the vertices.
 4. Z = P_0 R.  Reading: P_0 is the exact inverse of A_c (a dense Cholesky
    factorisation, FP64), so that the preconditioner is a fixed symmetric
-   linear operator; the paper's algebraic multigrid approximates it.
+   linear operator; the paper's algebraic multigrid approximates it
+   (solver="amg": one K-cycle of :mod:`oracle.amg`).
 5. Prolongation: Z scattered to Z_{IJK;e}; z_{ijk;e} = sum_IJK B_{IJK,ijk}
    Z_{IJK;e} m_{ijk;e}; gathered (summed) to z_N; and the coarse correction is
    z_N / m_N.  (The paper says "scatter" and "y_N" in this last step; the
@@ -76,7 +77,7 @@ def coarse_matrix(vtx, hexes, n_vertices: int, kappa=1.0, c=0.0) -> scipy.sparse
 
 class CoarseCorrection:
     def __init__(self, num: Numbering, geo: Geometry, gll: GLL, vtx, hexes, m_global,
-                 dirichlet=None, kappa=1.0, c=0.0):
+                 dirichlet=None, kappa=1.0, c=0.0, solver="exact"):
         self.num = num
         self.geo = geo
         self.B = vandermonde(gll)
@@ -88,8 +89,15 @@ class CoarseCorrection:
         self.free = np.nonzero(dirichlet[:nv] == 0)[0]
         A = coarse_matrix(vtx, hexes, nv, kappa, c)
         self.A_full = A
-        self.Ac = A[self.free][:, self.free].toarray()
-        self.chol = scipy.linalg.cho_factor(self.Ac, lower=True) if self.free.size else None
+        self.solver = solver
+        if solver == "amg":
+            from .amg import KCycle
+            self.Ac = A[self.free][:, self.free].tocsr()
+            self.kcycle = KCycle(self.Ac) if self.free.size else None
+            self.chol = None
+        else:
+            self.Ac = A[self.free][:, self.free].toarray()
+            self.chol = scipy.linalg.cho_factor(self.Ac, lower=True) if self.free.size else None
 
     def restrict(self, r: np.ndarray) -> np.ndarray:
         """Global coarse residual R on all vertices (step 3)."""
@@ -103,7 +111,10 @@ class CoarseCorrection:
     def solve(self, R: np.ndarray) -> np.ndarray:
         """Z = A_c^{-1} R on free vertices, 0 on Dirichlet vertices (step 4)."""
         Z = np.zeros_like(R)
-        if self.chol is not None:
+        if self.solver == "amg":
+            if self.kcycle is not None:
+                Z[self.free] = self.kcycle(R[self.free])
+        elif self.chol is not None:
             Z[self.free] = scipy.linalg.cho_solve(self.chol, R[self.free])
         return Z
 

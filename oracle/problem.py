@@ -21,7 +21,8 @@ from .schwarz import FinePreconditioner
 
 
 class Problem:
-    def __init__(self, vtx, hexes, n, fine=True, coarse=True, dirichlet=None, kappa=1.0, c=0.0):
+    def __init__(self, vtx, hexes, n, fine=True, coarse=True, dirichlet=None, kappa=1.0, c=0.0,
+                 coarse_solver="exact"):
         self.vtx = np.asarray(vtx, dtype=np.float64)
         self.hexes = np.asarray(hexes, dtype=np.int64)
         self.n = n
@@ -36,6 +37,7 @@ class Problem:
         self.c = float(c) if np.ndim(c) == 0 else np.asarray(c, dtype=np.float64).reshape(E)
         self._fine_on = fine
         self._coarse_on = coarse
+        self.coarse_solver = coarse_solver
         self._fine = None
         self._coarse = None
 
@@ -50,7 +52,7 @@ class Problem:
     def coarse(self):
         if self._coarse is None and self._coarse_on:
             self._coarse = CoarseCorrection(self.num, self.geo, self.gll, self.vtx, self.hexes,
-                                            self.m, self.dirichlet, self.kappa, self.c)
+                                            self.m, self.dirichlet, self.kappa, self.c, self.coarse_solver)
         return self._coarse
 
     def A(self, u):
