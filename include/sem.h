@@ -226,6 +226,29 @@ int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa_host, cons
 int sem_mesh_boundary_face_mass(sem_mesh m, const int64_t* faces_host, int64_t n_faces, double* ws_host);
 
 /*
+ * sem_mesh_set_coarse_solver -- P_0 of eq. (coarse).  SEM_COARSE_EXACT
+ * (default): the exact inverse of the order-1 matrix (nested dissection,
+ * FP64).  SEM_COARSE_AMG: one K-cycle of an aggregation-based algebraic
+ * multigrid on it (Section 4.1, "Algebraic multigrid"): double pairwise
+ * aggregation of the strong negative couplings (threshold 0.25), Galerkin
+ * coarse matrices, damped Jacobi (omega = 2/3, one sweep before and one
+ * after), two flexible-CG steps per level, the coarsest level (<= 400
+ * unknowns) solved exactly; built on the host, applied on the device as one
+ * captured graph, rebuilt whenever the coarse matrix changes.  P_0 is then
+ * nonlinear and the PCG iterates differ from the exact case; the solution to
+ * a given tolerance is the same.  Synchronises the device.
+ * Errors: SEM_EINVAL (unknown solver), SEM_ENOMEM, SEM_EHIP, SEM_EMESH.
+ */
+enum sem_coarse_solver { SEM_COARSE_EXACT = 0, SEM_COARSE_AMG = 1 };
+int sem_mesh_set_coarse_solver(sem_mesh m, int solver);
+
+/* The AMG hierarchy the handle would build (host only, for checks): number
+   of levels, the first `cap` level sizes (level 0 = free vertices), and, when
+   agg0 != NULL and there are two levels or more, the aggregate of each level-0
+   unknown ([level_sizes[0]], unknowns in ascending vertex id). */
+int sem_mesh_amg_hierarchy(sem_mesh m, int64_t* level_sizes_host, int cap, int* n_levels, int32_t* agg0_host);
+
+/*
  * sem_heat_step -- one backward Euler step of the heat equation (Section 6.2):
  * solves (kappa A + M / dt) u_next = M (u_prev / dt + q) with u = 0 on the
  * Dirichlet set, where M is the lumped mass m_N.  Sets the coefficients to

@@ -25,7 +25,7 @@ FLAGS = [
     "-Wno-unused-result",
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocblas", "-lrocsolver", "-lpthread", "-Wl,-rpath,/opt/rocm/lib"]
-SOURCES = ["sem_device.hip", "sem_batch.hip", "sem_setup.cpp"]
+SOURCES = ["sem_device.hip", "sem_batch.hip", "sem_setup.cpp", "sem_amg.cpp"]
 
 
 def build(verbose: bool = True) -> str:

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <memory>
+
 #include <functional>
 #include <string>
 
@@ -93,6 +95,18 @@ struct sem_mesh_s {
   bool per_elem = false, any_ce = false;
   DBuf<double> ke64, ce64, mL64;
   DBuf<float> ke32, ce32, mL32;
+  // coarse solver: 0 exact (nested dissection), 1 aggregation AMG with a K-cycle
+  int coarse_solver = 0;
+  struct AmgDev {
+    int64_t n = 0;
+    DBuf<int32_t> off, col, agg, moff, mem;
+    DBuf<double> val, wd;
+    DBuf<double> B, X, R, T, V, W, B2, V2, W2;  // cycle input/output/temporaries, flexible-CG vectors
+  };
+  std::vector<std::unique_ptr<AmgDev>> amg;
+  DBuf<double> amg_inv, amg_sc;
+  DBuf<int32_t> amg_nd, amg_pos;
+  hipGraphExec_t amg_graph = nullptr;
   // PCG work
   DBuf<double> v64[5];
   DBuf<float> v32[5];

@@ -359,10 +359,140 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
 void release_coarse_graph(sem_mesh m) {
   if (m->coarse_graph) (void)hipGraphExecDestroy(m->coarse_graph);
   m->coarse_graph = nullptr;
+  if (m->amg_graph) (void)hipGraphExecDestroy(m->amg_graph);
+  m->amg_graph = nullptr;
+}
+
+// --- aggregation AMG (Section 4.1, "Algebraic multigrid") ------------------
+constexpr double kAmgOmega = 2.0 / 3.0;  // damped Jacobi
+
+// host hierarchy -> device (work vectors per level, Jacobi weights omega / a_ii)
+void amg_setup(sem_mesh m) {
+  const HostTables& T = m->T;
+  m->amg.clear();
+  if (T.nc == 0) return;
+  AmgHierarchy H;
+  build_amg(T, H);
+  for (const AmgLevel& L : H.levels) {
+    auto d = std::make_unique<sem_mesh_s::AmgDev>();
+    d->n = L.n;
+    d->off.upload(L.off.data(), L.off.size());
+    d->col.upload(L.col.data(), L.col.size());
+    d->val.upload(L.val.data(), L.val.size());
+    std::vector<double> wd(L.n);
+    for (int64_t i = 0; i < L.n; ++i) wd[i] = kAmgOmega / L.diag[i];
+    d->wd.upload(wd.data(), wd.size());
+    if (!L.agg.empty()) {
+      d->agg.upload(L.agg.data(), L.agg.size());
+      d->moff.upload(L.moff.data(), L.moff.size());
+      d->mem.upload(L.mem.data(), L.mem.size());
+    }
+    for (DBuf<double>* b : {&d->B, &d->X, &d->R, &d->T, &d->V, &d->W, &d->B2, &d->V2, &d->W2}) b->alloc(L.n);
+    m->amg.push_back(std::move(d));
+  }
+  m->amg_inv.upload(H.coarse_inv.data(), H.coarse_inv.size());
+  m->amg_sc.alloc(5 * H.levels.size());
+  m->amg_nd.upload(H.nd_of.data(), H.nd_of.size());
+  std::vector<int32_t> pos(T.nc);
+  for (size_t q = 0; q < H.nd_of.size(); ++q) pos[H.nd_of[q]] = (int32_t)q;
+  m->amg_pos.upload(pos.data(), pos.size());
+}
+
+void amg_fcg2(sem_mesh m, int l, const double* b, double* x, hipStream_t s);
+
+// one K-cycle on level l: x ~= A_l^{-1} b
+void amg_kcycle(sem_mesh m, int l, const double* b, double* x, hipStream_t s) {
+  const int L = (int)m->amg.size() - 1;
+  auto& d = *m->amg[l];
+  const int64_t n = d.n;
+  const unsigned g = (unsigned)blocks_for(n);
+  if (l == L) {
+    hipLaunchKernelGGL(amg_gemv_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, x, m->amg_inv.p, b, n);
+    SEM_HIP(hipGetLastError());
+    return;
+  }
+  auto& c = *m->amg[l + 1];
+  hipLaunchKernelGGL(amg_scale_kernel, dim3(g), dim3(kGS), 0, s, x, b, d.wd.p, n);
+  hipLaunchKernelGGL(amg_residual_kernel, dim3(g), dim3(kGS), 0, s, d.R.p, b, x, d.off.p, d.col.p, d.val.p, n);
+  hipLaunchKernelGGL(amg_restrict_kernel, dim3((unsigned)blocks_for(c.n)), dim3(kGS), 0, s, c.B.p, d.R.p, d.moff.p,
+                     d.mem.p, c.n);
+  SEM_HIP(hipGetLastError());
+  if (l + 1 == L)
+    amg_kcycle(m, l + 1, c.B.p, c.X.p, s);
+  else
+    amg_fcg2(m, l + 1, c.B.p, c.X.p, s);
+  hipLaunchKernelGGL(amg_prolong_kernel, dim3(g), dim3(kGS), 0, s, d.T.p, x, c.X.p, d.agg.p, n);
+  hipLaunchKernelGGL(amg_post_kernel, dim3(g), dim3(kGS), 0, s, x, d.T.p, b, d.off.p, d.col.p, d.val.p, d.wd.p, n);
+  SEM_HIP(hipGetLastError());
+}
+
+// two flexible-CG steps on level l preconditioned by the K-cycle of level l
+void amg_fcg2(sem_mesh m, int l, const double* b, double* x, hipStream_t s) {
+  auto& d = *m->amg[l];
+  const int64_t n = d.n;
+  const unsigned g = (unsigned)blocks_for(n);
+  double* sc = m->amg_sc.p + 5 * l;
+  amg_kcycle(m, l, b, d.V.p, s);
+  hipLaunchKernelGGL(amg_spmv_kernel, dim3(g), dim3(kGS), 0, s, d.W.p, d.V.p, d.off.p, d.col.p, d.val.p, n);
+  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 0, d.V.p, b, n);
+  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 1, d.V.p, d.W.p, n);
+  hipLaunchKernelGGL(amg_r2_kernel, dim3(g), dim3(kGS), 0, s, d.B2.p, b, d.W.p, sc, n);
+  SEM_HIP(hipGetLastError());
+  amg_kcycle(m, l, d.B2.p, d.V2.p, s);
+  hipLaunchKernelGGL(amg_spmv_kernel, dim3(g), dim3(kGS), 0, s, d.W2.p, d.V2.p, d.off.p, d.col.p, d.val.p, n);
+  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 2, d.V2.p, d.W.p, n);
+  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 3, d.V2.p, d.W2.p, n);
+  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 4, d.V2.p, d.B2.p, n);
+  hipLaunchKernelGGL(amg_combine_kernel, dim3(g), dim3(kGS), 0, s, x, d.V.p, d.V2.p, sc, n);
+  SEM_HIP(hipGetLastError());
+}
+
+// Rlev (coarse order) -> Zv (vertex order) by one K-cycle
+void amg_sweeps(sem_mesh m, hipStream_t s) {
+  const HostTables& T = m->T;
+  auto& d0 = *m->amg[0];
+  hipLaunchKernelGGL(amg_in_kernel, dim3((unsigned)blocks_for(d0.n)), dim3(kGS), 0, s, d0.B.p, m->Rlev.p,
+                     m->amg_nd.p, d0.n);
+  amg_kcycle(m, 0, d0.B.p, d0.X.p, s);
+  hipLaunchKernelGGL(amg_out_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, d0.X.p, m->cidx.p,
+                     m->amg_pos.p, T.V);
+  SEM_HIP(hipGetLastError());
+}
+
+void amg_solve(sem_mesh m, hipStream_t s) {
+  if (m->amg.empty()) throw Error{SEM_EINVAL, "AMG hierarchy not built"};
+  if (m->direct_coarse) {
+    amg_sweeps(m, s);
+    return;
+  }
+  if (!m->amg_graph) {
+    if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    SEM_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      amg_sweeps(m, m->capture_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(m->capture_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SEM_HIP(hipStreamEndCapture(m->capture_stream, &g));
+    hipError_t err = hipGraphInstantiate(&m->amg_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (err != hipSuccess) {
+      m->amg_graph = nullptr;
+      throw Error{SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
+    }
+  }
+  SEM_HIP(hipGraphLaunch(m->amg_graph, s));
 }
 
 // capture the sweeps once (on a private stream) and replay them on the caller's stream
 void coarse_solve_tree(sem_mesh m, hipStream_t s) {
+  if (m->coarse_solver == SEM_COARSE_AMG) {
+    amg_solve(m, s);
+    return;
+  }
   if (m->direct_coarse) {
     coarse_sweeps(m, s);
     return;
@@ -461,6 +591,7 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
 void factor_coarse(sem_mesh m) {
   HostTables& T = m->T;
   release_coarse_graph(m);
+  if (m->coarse_solver == SEM_COARSE_AMG) amg_setup(m);
   m->cidx.upload(T.cidx.data(), T.cidx.size());
   const size_t nc = std::max<int64_t>(T.nc, 1);
   m->Rlev.alloc(nc);
@@ -1389,6 +1520,43 @@ int sem_mesh_boundary_face_mass(sem_mesh m, const int64_t* faces, int64_t n_face
   if (!m || !ws || n_faces < 0 || (n_faces > 0 && !faces)) return SEM_EINVAL;
   return guarded([&]() -> int {
     boundary_face_mass(m->T, faces, n_faces, ws);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_set_coarse_solver(sem_mesh m, int solver) {
+  if (!m || (solver != SEM_COARSE_EXACT && solver != SEM_COARSE_AMG)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    if (m->coarse_solver == solver) return SEM_OK;
+    m->coarse_solver = solver;
+    if (m->host_only) return SEM_OK;
+    SEM_HIP(hipSetDevice(m->device));
+    SEM_HIP(hipDeviceSynchronize());
+    release_coarse_graph(m);
+    if (solver == SEM_COARSE_AMG) {
+      try {
+        amg_setup(m);
+      } catch (...) {
+        m->coarse_solver = SEM_COARSE_EXACT;
+        m->amg.clear();
+        throw;
+      }
+    } else {
+      m->amg.clear();
+    }
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_amg_hierarchy(sem_mesh m, int64_t* level_sizes, int cap, int* n_levels, int32_t* agg0) {
+  if (!m || !n_levels || cap < 0 || (cap > 0 && !level_sizes)) return SEM_EINVAL;
+  return guarded([&]() -> int {
+    AmgHierarchy H;
+    build_amg(m->T, H);
+    *n_levels = (int)H.levels.size();
+    for (int l = 0; l < cap && l < (int)H.levels.size(); ++l) level_sizes[l] = H.levels[l].n;
+    if (agg0 && !H.levels.empty() && !H.levels[0].agg.empty())
+      std::copy(H.levels[0].agg.begin(), H.levels[0].agg.end(), agg0);
     return SEM_OK;
   });
 }

@@ -146,6 +146,24 @@ struct HostTables {
   std::vector<double> kap_e, c_e;
 };
 
+// aggregation AMG hierarchy of the coarse system (sem_amg.cpp); level 0 holds
+// the free vertices in ascending vertex id
+struct AmgLevel {
+  int64_t n = 0;
+  std::vector<int32_t> off, col;  // CSR, columns ascending
+  std::vector<double> val, diag;
+  std::vector<int32_t> agg;       // [n] aggregate (row of the next level); empty on the coarsest
+  std::vector<int32_t> moff, mem; // members of each aggregate, ascending
+};
+
+struct AmgHierarchy {
+  std::vector<AmgLevel> levels;
+  std::vector<double> coarse_inv;  // dense inverse of the coarsest matrix, row-major
+  std::vector<int32_t> nd_of;      // level-0 unknown -> coarse (nested-dissection) index
+};
+
+void build_amg(const HostTables& T, AmgHierarchy& H);
+
 // host set-up entry points (sem_setup.cpp)
 void build_reference(HostTables& T, int N);
 void build_numbering(HostTables& T, const int64_t* hex, int64_t n_hex, int64_t n_vtx);

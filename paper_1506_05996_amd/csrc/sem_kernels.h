@@ -999,6 +999,133 @@ coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const do
   if (lane == 0) X[nd.off + ri.row] = Z[nd.off + ri.row] - v;
 }
 
+// ---------------------------------------------------------------------------
+// Aggregation AMG with a K-cycle on the coarse system (Section 4.1, "Algebraic
+// multigrid"): CSR matrices per level (columns ascending), damped Jacobi with
+// wd = omega / a_ii, restriction by aggregate sums (members ascending),
+// prolongation by injection.  All scalars of the flexible-CG steps stay on the
+// device, so a whole cycle can be captured in a graph.
+// ---------------------------------------------------------------------------
+// x = wd .* b  (Jacobi sweep from zero)
+__global__ void __launch_bounds__(256)
+amg_scale_kernel(double* __restrict__ x, const double* __restrict__ b, const double* __restrict__ wd, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = wd[i] * b[i];
+}
+
+// r = b - A x
+__global__ void __launch_bounds__(256)
+amg_residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ x,
+                    const int32_t* __restrict__ off, const int32_t* __restrict__ col, const double* __restrict__ val,
+                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int32_t q = off[i]; q < off[i + 1]; ++q) acc += val[q] * x[col[q]];
+  r[i] = b[i] - acc;
+}
+
+// w = A v
+__global__ void __launch_bounds__(256)
+amg_spmv_kernel(double* __restrict__ w, const double* __restrict__ v, const int32_t* __restrict__ off,
+                const int32_t* __restrict__ col, const double* __restrict__ val, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int32_t q = off[i]; q < off[i + 1]; ++q) acc += val[q] * v[col[q]];
+  w[i] = acc;
+}
+
+// B[a] = sum of r over the members of aggregate a
+__global__ void __launch_bounds__(256)
+amg_restrict_kernel(double* __restrict__ B, const double* __restrict__ r, const int32_t* __restrict__ moff,
+                    const int32_t* __restrict__ mem, int64_t nc) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nc) return;
+  double acc = 0.0;
+  for (int32_t q = moff[a]; q < moff[a + 1]; ++q) acc += r[mem[q]];
+  B[a] = acc;
+}
+
+// t = x + X[agg]  (coarse correction by injection)
+__global__ void __launch_bounds__(256)
+amg_prolong_kernel(double* __restrict__ t, const double* __restrict__ x, const double* __restrict__ X,
+                   const int32_t* __restrict__ agg, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = x[i] + X[agg[i]];
+}
+
+// x = t + wd .* (b - A t)  (Jacobi sweep after the coarse correction)
+__global__ void __launch_bounds__(256)
+amg_post_kernel(double* __restrict__ x, const double* __restrict__ t, const double* __restrict__ b,
+                const int32_t* __restrict__ off, const int32_t* __restrict__ col, const double* __restrict__ val,
+                const double* __restrict__ wd, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  for (int32_t q = off[i]; q < off[i + 1]; ++q) acc += val[q] * t[col[q]];
+  x[i] = t[i] + wd[i] * (b[i] - acc);
+}
+
+// sc[idx] = a . b over n entries, one workgroup, fixed summation order
+__global__ void __launch_bounds__(1024)
+amg_dot_kernel(double* __restrict__ sc, int idx, const double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+  __shared__ double red[1024 / 64];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += a[i] * b[i];
+  const double t = group_sum<1024>(acc, red);
+  if (threadIdx.x == 0) sc[idx] = t;
+}
+
+// r2 = b - (rho / a1) w   with sc = {rho, a1, ...}
+__global__ void __launch_bounds__(256)
+amg_r2_kernel(double* __restrict__ r2, const double* __restrict__ b, const double* __restrict__ w,
+              const double* __restrict__ sc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r2[i] = b[i] - (sc[0] / sc[1]) * w[i];
+}
+
+// two flexible-CG steps combined: x = (rho/a1) v + (a2/den) (v2 - (g/a1) v),
+// den = be - g^2/a1, with sc = {rho, a1, g, be, a2}
+__global__ void __launch_bounds__(256)
+amg_combine_kernel(double* __restrict__ x, const double* __restrict__ v, const double* __restrict__ v2,
+                   const double* __restrict__ sc, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double rho = sc[0], a1 = sc[1], g = sc[2], be = sc[3], a2 = sc[4];
+  const double den = be - g * g / a1;
+  x[i] = (rho / a1) * v[i] + (a2 / den) * (v2[i] - (g / a1) * v[i]);
+}
+
+// x = Ainv b, dense row-major n x n; one wave per row
+__global__ void __launch_bounds__(256)
+amg_gemv_kernel(double* __restrict__ x, const double* __restrict__ Ainv, const double* __restrict__ b, int64_t n) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;  // whole wave
+  double acc = 0.0;
+  for (int64_t k = lane; k < n; k += 64) acc += Ainv[row * n + k] * b[k];
+  acc = wave_sum(acc);
+  if (lane == 0) x[row] = acc;
+}
+
+// level-0 right-hand side from the coarse residual (nested-dissection order)
+__global__ void __launch_bounds__(256)
+amg_in_kernel(double* __restrict__ B0, const double* __restrict__ R, const int32_t* __restrict__ nd_of, int64_t n) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) B0[q] = R[nd_of[q]];
+}
+
+// vertex-indexed result (0 on Dirichlet vertices) from the level-0 solution
+__global__ void __launch_bounds__(256)
+amg_out_kernel(double* __restrict__ Zv, const double* __restrict__ X0, const int32_t* __restrict__ cidx,
+               const int32_t* __restrict__ pos, int64_t V) {
+  const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= V) return;
+  const int32_t c = cidx[v];
+  Zv[v] = c >= 0 ? X0[pos[c]] : 0.0;
+}
+
 // vertex-indexed coarse solution (0 on Dirichlet vertices)
 __global__ void __launch_bounds__(256)
 coarse_scatter_kernel(double* __restrict__ Zv, const double* __restrict__ X, const int32_t* __restrict__ cidx,

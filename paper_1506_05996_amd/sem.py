@@ -37,7 +37,8 @@ EXPORTS = [
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
-    "sem_mesh_set_element_coefficients", "sem_mesh_boundary_face_mass",
+    "sem_mesh_set_element_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
+    "sem_mesh_amg_hierarchy",
 ]
 
 
@@ -89,10 +90,13 @@ _lib.sem_mesh_set_coefficients.argtypes = [_p, ctypes.c_double, ctypes.c_double]
 _lib.sem_mesh_coefficients.argtypes = [_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.sem_mesh_set_element_coefficients.argtypes = [_p, _p, _p]
 _lib.sem_mesh_boundary_face_mass.argtypes = [_p, _p, _i64, _p]
+_lib.sem_mesh_set_coarse_solver.argtypes = [_p, ctypes.c_int]
+_lib.sem_mesh_amg_hierarchy.argtypes = [_p, _p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _p]
 _lib.sem_heat_step.argtypes = [_p, ctypes.c_double, ctypes.c_double, _p, _p, _p, ctypes.POINTER(SolveOpts),
                                ctypes.POINTER(SolveStats), _p]
 _lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
 TILE_MFMA = 16
+COARSE_EXACT, COARSE_AMG = 0, 1  # sem_coarse_solver
 TILE_GEO = 32  # operator tile that rebuilds the geometric factors from the vertices
 
 
@@ -306,6 +310,24 @@ class Mesh:
         _check(_lib.sem_mesh_boundary_face_mass(self._h, f.ctypes.data_as(ctypes.c_void_p), int(f.shape[0]),
                                                 ws.ctypes.data_as(ctypes.c_void_p)))
         return ws
+
+    def set_coarse_solver(self, solver):
+        """P_0: COARSE_EXACT (nested-dissection inverse) or COARSE_AMG (one K-cycle)."""
+        _check(_lib.sem_mesh_set_coarse_solver(self._h, int(solver)))
+
+    def amg_hierarchy(self, cap=32):
+        """(level sizes, aggregates of the level-0 unknowns or None), built on the host."""
+        sizes = np.zeros(cap, dtype=np.int64)
+        nl = ctypes.c_int()
+        _check(_lib.sem_mesh_amg_hierarchy(self._h, sizes.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(nl),
+                                           None))
+        sizes = sizes[:min(nl.value, cap)]
+        agg = None
+        if nl.value >= 2:
+            agg = np.empty(int(sizes[0]), dtype=np.int32)
+            _check(_lib.sem_mesh_amg_hierarchy(self._h, sizes.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(nl),
+                                               agg.ctypes.data_as(ctypes.c_void_p)))
+        return sizes, agg
 
     def coefficients(self):
         k, c = ctypes.c_double(), ctypes.c_double()

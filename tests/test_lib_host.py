@@ -189,3 +189,23 @@ def test_element_coefficients_validation_on_a_host_handle():
         M.set_element_coefficients(np.ones(E + 1), None)
     M.set_coefficients(1.0, 0.0)
     assert M.coefficients() == (1.0, 0.0)
+
+
+@pytest.mark.parametrize("k,perturb,seed", [(10, 0.12, 3), (14, 0.15, 5)])
+def test_amg_hierarchy_bit_exact(k, perturb, seed):
+    # level sizes and level-0 aggregates equal the oracle's (same readings,
+    # independent implementations; unknowns in ascending vertex id)
+    from oracle.amg import hierarchy
+    from oracle.coarse import coarse_matrix
+    from oracle.numbering import number_mesh
+    m = meshgen.cube_mesh(k, perturb=perturb, seed=seed)
+    m, _ = meshgen.rotate_elements(m, seed=49)
+    M = sem.Mesh(m.vtx, m.hex, 2, host_only=True)
+    sizes, agg0 = M.amg_hierarchy()
+    num = number_mesh(m.hex, 1)
+    A = coarse_matrix(m.vtx, m.hex, num.n_global).tocsr()
+    free = np.nonzero(num.dirichlet == 0)[0]
+    As, aggs = hierarchy(A[free][:, free].tocsr())
+    assert list(sizes) == [a.shape[0] for a in As]
+    assert len(sizes) >= 2
+    assert np.array_equal(agg0, aggs[0])
