@@ -12,7 +12,8 @@ launch stream give the per-kernel durations used for the roofline entry.
 After the timed region, time-to-tolerance of the PCG solve (||b - A x|| /
 ||b|| <= 1e-10, true residual) is measured in plain FP64 and in the
 FP32-refined form: one untimed warm-up solve per form, then the median of
-`--pcg-reps` solves.  Then a solve with one kappa per element and a Neumann
+`--pcg-reps` solves, and once more with the aggregation-AMG coarse solver
+(`pcg.amg_coarse_solver`).  Then a solve with one kappa per element and a Neumann
 face (`coefficients`), and the heat-equation run (Section 6.2) on a
 synthetic rod of 62,500 hexahedra at N = 7: 70 backward Euler steps, each a
 PCG solve to 1e-10, in FP64 and FP32-refined form (`heat` in the output).
@@ -165,6 +166,57 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def run_amg(M, b, dev, args):
+    """The coarse solve P_0 as one K-cycle of the aggregation AMG instead of the
+    exact inverse: hierarchy, time per application of P_0 (HIP events over 20
+    replays of the captured cycle), and PCG to 1e-10 with it in both forms."""
+    import numpy as np
+    import torch
+
+    from paper_1506_05996_amd import sem
+
+    t0 = time.time()
+    M.set_coarse_solver(sem.COARSE_AMG)
+    setup = time.time() - t0
+    sizes, _ = M.amg_hierarchy()
+    R = torch.tensor(np.random.default_rng(1508).uniform(-1, 1, M.n_vertices), device=dev)
+    Z = torch.empty_like(R)
+    M.coarse_solve(R, Z)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        M.coarse_solve(R, Z)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 20
+    M.set_coarse_solver(sem.COARSE_EXACT)
+    M.coarse_solve(R, Z)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(20):
+        M.coarse_solve(R, Z)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_exact = ev0.elapsed_time(ev1) / 20
+    M.set_coarse_solver(sem.COARSE_AMG)
+    res = {"levels": [int(v) for v in sizes], "setup_s": round(setup, 2), "ms_per_P0": round(ms, 3),
+           "ms_per_exact_coarse_solve": round(ms_exact, 3)}
+    for name, mode in (("fp64", sem.SOLVE_FP64), ("fp32_refined", sem.SOLVE_FP32_REFINED)):
+        kw = dict(mode=mode, rtol=1e-10, max_iter=2000, inner_rtol=args.inner_rtol, max_outer=40)
+        M.solve(b, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, info = M.solve(b, **kw)
+        torch.cuda.synchronize()
+        res[name] = {"time_s": round(time.perf_counter() - t0, 4), "iterations": info["iterations"],
+                     "outer": info["outer"], "rel_residual": info["rel_residual"]}
+        log(f"[bench] AMG coarse solver {name}: {res[name]}")
+    M.set_coarse_solver(sem.COARSE_EXACT)
+    log(f"[bench] AMG: levels {res['levels']}, P_0 {ms:.3f} ms vs exact {ms_exact:.3f} ms")
+    return res
+
+
 def run_coefficients(M, mesh, dev, args):
     """Per-element coefficients and Neumann data on the same mesh: kappa_e
     log-uniform in [0.1, 10] (seed 1507; 1 on the elements with a face on
@@ -281,6 +333,7 @@ def main():
     ap.add_argument("--inner-rtol", type=float, default=3e-3, help="refined form: tolerance of each FP32 inner solve")
     ap.add_argument("--no-serial", action="store_true", help="batch64: skip the one-by-one comparison")
     ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation run on the rod")
+    ap.add_argument("--no-amg", action="store_true", help="skip the PCG runs with the AMG coarse solver")
     ap.add_argument("--no-coef", action="store_true",
                     help="skip the per-element-coefficient / Neumann solve on the main mesh")
     ap.add_argument("--counters", action="store_true",
@@ -409,6 +462,8 @@ def main():
                          "err_l2m_vs_exact": el2, "reps": len(times)}
             log(f"[bench] PCG {name}: {pcg[name]}")
         pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
+        if not args.no_amg:
+            pcg["amg_coarse_solver"] = run_amg(M, b, dev, args)
         del b, ue_d, mN
 
     coefs = None
