@@ -67,3 +67,31 @@ def test_amg_coarse_solver(name, kw, N):
     M.set_coarse_solver(sem.COARSE_EXACT)
     Z = M.coarse_solve(torch.tensor(R, device=dev)).cpu().numpy()
     assert rel_l2(Z, P_exact.coarse.solve(R)) <= 1e-12
+
+
+def test_amg_with_element_coefficients_and_partial_dirichlet():
+    # the hierarchy is rebuilt when the coarse matrix changes (coefficients,
+    # Dirichlet set); P_0 and the solution follow the oracle
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(12, perturb=0.12, seed=8)
+    m, _ = meshgen.rotate_elements(m, seed=52)
+    E = len(m.hex)
+    kap = 10.0 ** np.random.default_rng(9).uniform(-1, 1, E)
+    M = sem.Mesh(m.vtx, m.hex, 2)
+    M.set_coarse_solver(sem.COARSE_AMG)
+    M.set_element_coefficients(kap, None)
+    x = M.node_coords()
+    dirichlet = ((np.abs(x[:, 0]) <= 1e-12) | (np.abs(x[:, 0] - 1) <= 1e-12)).astype(np.uint8)
+    M.set_dirichlet(dirichlet)
+    P = Problem(m.vtx, m.hex, 2, dirichlet=dirichlet, kappa=kap, coarse_solver="amg")
+    assert P.coarse.kcycle.L >= 1
+    R = np.random.default_rng(41).uniform(-1, 1, M.n_vertices)
+    Z = M.coarse_solve(torch.tensor(R, device=dev)).cpu().numpy()
+    assert rel_l2(Z, P.coarse.solve(R)) <= 1e-10
+    b = M.lumped_mass() * 1.0
+    b[dirichlet.astype(bool)] = 0.0
+    P_exact = Problem(m.vtx, m.hex, 2, dirichlet=dirichlet, kappa=kap)
+    ue, _, _, _ = P_exact.solve(b, rtol=1e-13)
+    xs, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    assert rel_l2(xs.cpu().numpy(), ue) <= 1e-10

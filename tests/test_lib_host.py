@@ -209,3 +209,26 @@ def test_amg_hierarchy_bit_exact(k, perturb, seed):
     assert list(sizes) == [a.shape[0] for a in As]
     assert len(sizes) >= 2
     assert np.array_equal(agg0, aggs[0])
+
+
+def test_amg_hierarchy_follows_element_coefficients_and_dirichlet_set():
+    from oracle.amg import hierarchy
+    from oracle.coarse import coarse_matrix
+    from oracle.numbering import number_mesh
+    m = meshgen.cube_mesh(12, perturb=0.12, seed=8)
+    E = len(m.hex)
+    kap = 10.0 ** np.random.default_rng(9).uniform(-1, 1, E)
+    M = sem.Mesh(m.vtx, m.hex, 2, host_only=True)
+    M.set_element_coefficients(kap, None)
+    # Dirichlet only on x = 0 and x = 1 (the other faces free)
+    x = M.node_coords()
+    dirichlet = ((np.abs(x[:, 0]) <= 1e-12) | (np.abs(x[:, 0] - 1) <= 1e-12)).astype(np.uint8)
+    M.set_dirichlet(dirichlet)
+    sizes, agg0 = M.amg_hierarchy()
+    num = number_mesh(m.hex, 1)
+    A = coarse_matrix(m.vtx, m.hex, num.n_global, kappa=kap).tocsr()
+    nv = num.n_global
+    free = np.nonzero(dirichlet[:nv] == 0)[0]
+    As, aggs = hierarchy(A[free][:, free].tocsr())
+    assert list(sizes) == [a.shape[0] for a in As] and len(sizes) >= 2
+    assert np.array_equal(agg0, aggs[0])
