@@ -104,3 +104,47 @@ def test_mixed_dirichlet_neumann_solve(N):
     err = np.abs(xs - meshgen.mixed_bc_u(x)).max()
     print(f"N={N} mixed-BC error vs exact {err:.2e}")
     assert err <= (1e-4 if N == 4 else 1e-6)
+
+
+def test_single_element_mesh():
+    # one hexahedron: every vertex is on the Dirichlet boundary, so the coarse
+    # space is empty and P = P^f; operator, preconditioner and solve still match
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(1, lengths=(1.0, 2.0, 0.5))
+    for N in (2, 7, 15):
+        M = sem.Mesh(m.vtx, m.hex, N)
+        P = Problem(m.vtx, m.hex, N)
+        assert M.n_vertices == 8
+        u = np.random.default_rng(60).uniform(-1, 1, M.n_global)
+        assert rel_l2(M.apply_A(torch.tensor(u, device=dev)).cpu().numpy(), P.A(u)) <= 1e-12
+        r = np.random.default_rng(61).uniform(-1, 1, M.n_global)
+        r[P.num.dirichlet.astype(bool)] = 0.0
+        z = M.precond(torch.tensor(r, device=dev)).cpu().numpy()
+        assert rel_l2(z, P.precond()(r)) <= 1e-12
+        b = P.load(lambda x: meshgen.manufactured_s(x, m.lengths))
+        ut, _, _, _ = P.solve(b, rtol=1e-13)
+        x, _ = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+        assert rel_l2(x.cpu().numpy(), ut) <= 1e-10
+
+
+def test_no_dirichlet_nodes_with_a_mass_term():
+    # c > 0 makes the problem definite without any Dirichlet node: every
+    # vertex is a coarse unknown and nothing is masked
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(3, perturb=0.1, seed=14)
+    N = 4
+    M = sem.Mesh(m.vtx, m.hex, N)
+    M.set_dirichlet(np.zeros(M.n_global, np.uint8))
+    M.set_coefficients(0.5, 3.0)
+    none = np.zeros(M.n_global, np.uint8)
+    P = Problem(m.vtx, m.hex, N, dirichlet=none, kappa=0.5, c=3.0)
+    u = np.random.default_rng(62).uniform(-1, 1, M.n_global)
+    assert rel_l2(M.apply_A(torch.tensor(u, device=dev)).cpu().numpy(), P.A(u)) <= 1e-12
+    z = M.precond(torch.tensor(u, device=dev)).cpu().numpy()
+    assert rel_l2(z, P.precond()(u)) <= 1e-12
+    b = M.lumped_mass() * np.cos(M.node_coords()[:, 0])
+    ut, _, _, _ = P.solve(b, rtol=1e-13)
+    x, _ = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    assert rel_l2(x.cpu().numpy(), ut) <= 1e-10

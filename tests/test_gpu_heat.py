@@ -107,4 +107,10 @@ def test_heat_steps_match_the_oracle(case):
     ur, info = M.heat_step(u_prev, dt, kappa, q=torch.tensor(src[-1], device=dev),
                            mode=sem.SOLVE_FP32_REFINED, rtol=1e-12)
     assert rel_l2(ur.cpu().numpy(), ref[-1]) <= 1e-9
+    # no source: pure decay from the last state, in place (u_next is u_prev)
+    u_last = torch.tensor(ref[-1], device=dev)
+    ref_decay, _ = heat.backward_euler(P, ref[-1], [np.zeros(M.n_global)], dt, rtol=1e-13)
+    u_dec, _ = M.heat_step(u_last, dt, kappa, q=None, u_next=u_last, rtol=1e-13)
+    assert u_dec.data_ptr() == u_last.data_ptr()
+    assert rel_l2(u_dec.cpu().numpy(), ref_decay[0]) <= 1e-10
     M.set_coefficients(1.0, 0.0)
