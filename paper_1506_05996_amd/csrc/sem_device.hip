@@ -412,8 +412,8 @@ void amg_kcycle(sem_mesh m, int l, const double* b, double* x, hipStream_t s) {
     return;
   }
   auto& c = *m->amg[l + 1];
-  hipLaunchKernelGGL(amg_scale_kernel, dim3(g), dim3(kGS), 0, s, x, b, d.wd.p, n);
-  hipLaunchKernelGGL(amg_residual_kernel, dim3(g), dim3(kGS), 0, s, d.R.p, b, x, d.off.p, d.col.p, d.val.p, n);
+  hipLaunchKernelGGL(amg_presmooth_kernel, dim3(g), dim3(kGS), 0, s, x, d.R.p, b, d.wd.p, d.off.p, d.col.p, d.val.p,
+                     n);
   hipLaunchKernelGGL(amg_restrict_kernel, dim3((unsigned)blocks_for(c.n)), dim3(kGS), 0, s, c.B.p, d.R.p, d.moff.p,
                      d.mem.p, c.n);
   SEM_HIP(hipGetLastError());
@@ -434,15 +434,14 @@ void amg_fcg2(sem_mesh m, int l, const double* b, double* x, hipStream_t s) {
   double* sc = m->amg_sc.p + 5 * l;
   amg_kcycle(m, l, b, d.V.p, s);
   hipLaunchKernelGGL(amg_spmv_kernel, dim3(g), dim3(kGS), 0, s, d.W.p, d.V.p, d.off.p, d.col.p, d.val.p, n);
-  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 0, d.V.p, b, n);
-  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 1, d.V.p, d.W.p, n);
+  hipLaunchKernelGGL((amg_dots_kernel<2>), dim3(1), dim3(1024), 0, s, sc, 0, d.V.p, b, (const double*)d.W.p,
+                     (const double*)nullptr, n);
   hipLaunchKernelGGL(amg_r2_kernel, dim3(g), dim3(kGS), 0, s, d.B2.p, b, d.W.p, sc, n);
   SEM_HIP(hipGetLastError());
   amg_kcycle(m, l, d.B2.p, d.V2.p, s);
   hipLaunchKernelGGL(amg_spmv_kernel, dim3(g), dim3(kGS), 0, s, d.W2.p, d.V2.p, d.off.p, d.col.p, d.val.p, n);
-  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 2, d.V2.p, d.W.p, n);
-  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 3, d.V2.p, d.W2.p, n);
-  hipLaunchKernelGGL(amg_dot_kernel, dim3(1), dim3(1024), 0, s, sc, 4, d.V2.p, d.B2.p, n);
+  hipLaunchKernelGGL((amg_dots_kernel<3>), dim3(1), dim3(1024), 0, s, sc, 2, d.V2.p, (const double*)d.W.p,
+                     (const double*)d.W2.p, (const double*)d.B2.p, n);
   hipLaunchKernelGGL(amg_combine_kernel, dim3(g), dim3(kGS), 0, s, x, d.V.p, d.V2.p, sc, n);
   SEM_HIP(hipGetLastError());
 }

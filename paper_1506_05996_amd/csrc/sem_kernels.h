@@ -1006,22 +1006,20 @@ coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const do
 // prolongation by injection.  All scalars of the flexible-CG steps stay on the
 // device, so a whole cycle can be captured in a graph.
 // ---------------------------------------------------------------------------
-// x = wd .* b  (Jacobi sweep from zero)
+// Jacobi sweep from zero and its residual in one pass: x = wd .* b,
+// r = b - A x (x at the neighbours formed on the fly)
 __global__ void __launch_bounds__(256)
-amg_scale_kernel(double* __restrict__ x, const double* __restrict__ b, const double* __restrict__ wd, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = wd[i] * b[i];
-}
-
-// r = b - A x
-__global__ void __launch_bounds__(256)
-amg_residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ x,
-                    const int32_t* __restrict__ off, const int32_t* __restrict__ col, const double* __restrict__ val,
-                    int64_t n) {
+amg_presmooth_kernel(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ b,
+                     const double* __restrict__ wd, const int32_t* __restrict__ off, const int32_t* __restrict__ col,
+                     const double* __restrict__ val, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
-  for (int32_t q = off[i]; q < off[i + 1]; ++q) acc += val[q] * x[col[q]];
+  for (int32_t q = off[i]; q < off[i + 1]; ++q) {
+    const int32_t j = col[q];
+    acc += val[q] * (wd[j] * b[j]);
+  }
+  x[i] = wd[i] * b[i];
   r[i] = b[i] - acc;
 }
 
@@ -1067,14 +1065,28 @@ amg_post_kernel(double* __restrict__ x, const double* __restrict__ t, const doub
   x[i] = t[i] + wd[i] * (b[i] - acc);
 }
 
-// sc[idx] = a . b over n entries, one workgroup, fixed summation order
+// sc[idx + k] = a . b_k over n entries for the K vectors b_0..b_{K-1} (K <= 3),
+// one workgroup, fixed summation order
+template <int K>
 __global__ void __launch_bounds__(1024)
-amg_dot_kernel(double* __restrict__ sc, int idx, const double* __restrict__ a, const double* __restrict__ b, int64_t n) {
+amg_dots_kernel(double* __restrict__ sc, int idx, const double* __restrict__ a, const double* __restrict__ b0,
+                const double* __restrict__ b1, const double* __restrict__ b2, int64_t n) {
   __shared__ double red[1024 / 64];
-  double acc = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 1024) acc += a[i] * b[i];
-  const double t = group_sum<1024>(acc, red);
-  if (threadIdx.x == 0) sc[idx] = t;
+  double acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    const double ai = a[i];
+    acc[0] += ai * b0[i];
+    if constexpr (K > 1) acc[1] += ai * b1[i];
+    if constexpr (K > 2) acc[2] += ai * b2[i];
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const double t = group_sum<1024>(acc[k], red);
+    if (threadIdx.x == 0) sc[idx + k] = t;
+    __syncthreads();  // red is reused by the next sum
+  }
 }
 
 // r2 = b - (rho / a1) w   with sc = {rho, a1, ...}
