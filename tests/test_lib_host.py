@@ -232,3 +232,16 @@ def test_amg_hierarchy_follows_element_coefficients_and_dirichlet_set():
     As, aggs = hierarchy(A[free][:, free].tocsr())
     assert list(sizes) == [a.shape[0] for a in As] and len(sizes) >= 2
     assert np.array_equal(agg0, aggs[0])
+
+
+def test_coarse_solver_selection_on_a_host_handle():
+    m = meshgen.cube_mesh(2, perturb=0.1)
+    M = sem.Mesh(m.vtx, m.hex, 3, host_only=True)
+    M.set_coarse_solver(sem.COARSE_AMG)
+    M.set_coarse_solver(sem.COARSE_EXACT)
+    for bad in (-1, 2, 7):
+        with pytest.raises(sem.SemError) as e:
+            M.set_coarse_solver(bad)
+        assert e.value.status == sem.SEM_EINVAL
+    sizes, agg0 = M.amg_hierarchy()
+    assert list(sizes) == [1] and agg0 is None  # one free vertex: the coarsest level at once
