@@ -338,6 +338,8 @@ def main():
                     help="skip the per-element-coefficient / Neumann solve on the main mesh")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
+    ap.add_argument("--fine-precond", type=int, default=0, metavar="K",
+                    help="profiling run: K applications of the patch-solve preconditioner (FP64, then FP32), no timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
@@ -377,6 +379,15 @@ def main():
             y.copy_(u)
         torch.cuda.synchronize()
         log(f"[bench] counters run done: copy bytes per launch {8 * ng} read + {8 * ng} written")
+        return
+    if args.fine_precond > 0:
+        # rocprofv3 runs of the patch solves alone (sem_precond with the fine part only)
+        for dt in (torch.float64, torch.float32):
+            ud, yd = u.to(dt), y.to(dt)
+            for _ in range(args.fine_precond):
+                M.precond(ud, yd, pc=sem.PC_FINE)
+        torch.cuda.synchronize()
+        log(f"[bench] fine-preconditioner run done: {args.fine_precond} applications per dtype")
         return
     for _ in range(args.warmup):
         M.apply_A(u, y)
