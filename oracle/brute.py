@@ -4,7 +4,8 @@ Test infrastructure.  Independent of the sum-factorised path in
 :mod:`oracle.operator`: each element matrix is built from full 3D basis
 gradients at every GLL quadrature point (no tensor-product shortcuts),
 
-    K_e[a, b] = sum_q w_q |J_q| (J_q^{-T} grad psi_a(q)) . (J_q^{-T} grad psi_b(q)),
+    K_e[a, b] = sum_q w_q |J_q| kappa_q (J_q^{-T} grad psi_a(q)) . (J_q^{-T} grad psi_b(q))
+              + sum_q w_q |J_q| c_q psi_a(q) psi_b(q),
 
 with psi_a = phi_i phi_j phi_k the nodal tensor basis of eq. (interp), the
 Jacobian rebuilt here corner by corner from the trilinear map, and then
@@ -38,7 +39,11 @@ def _jacobian_pointwise(Xc: np.ndarray, xi, eta, zeta) -> np.ndarray:
 
 
 def element_matrix(Xc: np.ndarray, gll: GLL, kappa=1.0, c=0.0) -> np.ndarray:
-    """Dense (n+1)^3 x (n+1)^3 element matrix; local index i + (n+1)j + (n+1)^2 k."""
+    """Dense (n+1)^3 x (n+1)^3 element matrix; local index i + (n+1)j + (n+1)^2 k.
+
+    kappa and c: constants, or their values at the quadrature points [k, j, i]."""
+    kq = np.broadcast_to(np.asarray(kappa, dtype=np.float64), (len(gll.t),) * 3)
+    cq = np.broadcast_to(np.asarray(c, dtype=np.float64), (len(gll.t),) * 3)
     t, rho = gll.t, gll.rho
     n1 = len(t)
     Dq = lagrange_derivative_matrix(t)  # Dq[l, i] = phi_i'(t_l)
@@ -59,7 +64,7 @@ def element_matrix(Xc: np.ndarray, gll: GLL, kappa=1.0, c=0.0) -> np.ndarray:
             grad[a, 2] = Vq[ql, i] * Vq[qm, j] * Dq[qn, k]
             vals[a] = Vq[ql, i] * Vq[qm, j] * Vq[qn, k]
         gp = grad @ JinvT.T  # rows: J^{-T} grad psi_a
-        K += w * kappa * (gp @ gp.T) + w * c * np.outer(vals, vals)
+        K += w * kq[qn, qm, ql] * (gp @ gp.T) + w * cq[qn, qm, ql] * np.outer(vals, vals)
     return K
 
 

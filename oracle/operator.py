@@ -8,9 +8,12 @@ Test infrastructure.  For each element, in this order:
    du/deta|_{ijk}  = sum_m D_{jm} u_{imk},
    du/dzeta|_{ijk} = sum_m D_{km} u_{ijm};
 3. A, B, C = G . (du/dxi, du/deta, du/dzeta) with the symmetric packing
-   G^1..G^6 (eq. (ABC));
+   G^1..G^6 (eq. (ABC)); with kappa given at every node (eq. (R) weights each
+   quadrature point by its own kappa_{ijk;e}) A, B, C are multiplied by it;
 4. r_{ijk;e} = kappa_e sum_m [D_{mi} A_{mjk} + D_{mj} B_{imk} + D_{mk} C_{ijm}]
-   + c_e m_{ijk;e} u_{ijk;e}                                       (Algorithm 2);
+   + c_e m_{ijk;e} u_{ijk;e}                                       (Algorithm 2),
+   kappa_e = 1 when kappa is per node, and c_{ijk;e} in place of c_e when c is
+   per node;
 5. gather r_N = sum of the local copies (eq. (gather)), then zero the
    Dirichlet nodes (the homogeneous Dirichlet condition u_0 = 0 of Section 2).
 
@@ -32,7 +35,10 @@ from .numbering import Numbering, gather
 
 def element_action(U: np.ndarray, G: np.ndarray, D: np.ndarray, kappa=None, c=None,
                    mass=None) -> np.ndarray:
-    """Local residual r_{ijk;e} for local values U[e, k, j, i] (steps 2-4)."""
+    """Local residual r_{ijk;e} for local values U[e, k, j, i] (steps 2-4).
+
+    kappa and c: None, one value per element [E], or one per node [E, k, j, i]."""
+    kap = None if kappa is None else np.asarray(kappa)
     ur = np.einsum("im,ekjm->ekji", D, U)
     us = np.einsum("jm,ekmi->ekji", D, U)
     ut = np.einsum("km,emji->ekji", D, U)
@@ -40,13 +46,16 @@ def element_action(U: np.ndarray, G: np.ndarray, D: np.ndarray, kappa=None, c=No
     A = G1 * ur + G2 * us + G3 * ut
     B = G2 * ur + G4 * us + G5 * ut
     C = G3 * ur + G5 * us + G6 * ut
+    if kap is not None and kap.ndim == 4:
+        A, B, C = kap * A, kap * B, kap * C
     r = (np.einsum("mi,ekjm->ekji", D, A)
          + np.einsum("mj,ekmi->ekji", D, B)
          + np.einsum("mk,emji->ekji", D, C))
-    if kappa is not None:
-        r = r * np.asarray(kappa)[:, None, None, None]
+    if kap is not None and kap.ndim == 1:
+        r = r * kap[:, None, None, None]
     if c is not None:
-        r = r + np.asarray(c)[:, None, None, None] * mass * U
+        cc = np.asarray(c)
+        r = r + (cc[:, None, None, None] if cc.ndim == 1 else cc) * mass * U
     return r
 
 

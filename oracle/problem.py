@@ -3,8 +3,10 @@
 Bundles the steps of Sections 2-4 for a given mesh and order: numbering,
 geometry, lumped mass, node coordinates, operator, two-scale preconditioner
 and PCG, for the model problem c u - div(kappa grad u) = s with kappa > 0 and
-c >= 0 constant or one value per element (eq. (pde), Algorithm 2; kappa = 1,
-c = 0 is the Poisson problem).
+c >= 0 constant, one value per element (Algorithm 2) or one value per node
+of every element (eq. (R)); kappa = 1, c = 0 is the Poisson problem.  With
+per-node values the patch solves and the coarse matrix take each element's
+mean (:func:`oracle.schwarz.element_mean`).
 Nothing here adds arithmetic of its own.
 """
 from __future__ import annotations
@@ -17,7 +19,7 @@ from .gll import GLL
 from .numbering import number_mesh
 from .operator import apply_A, load_vector
 from .pcg import TwoScale, pcg
-from .schwarz import FinePreconditioner
+from .schwarz import FinePreconditioner, element_mean
 
 
 class Problem:
@@ -33,8 +35,18 @@ class Problem:
         self.x = node_coords_global(self.num, self.geo)
         self.dirichlet = self.num.dirichlet if dirichlet is None else dirichlet
         E = len(self.hexes)
-        self.kappa = float(kappa) if np.ndim(kappa) == 0 else np.asarray(kappa, dtype=np.float64).reshape(E)
-        self.c = float(c) if np.ndim(c) == 0 else np.asarray(c, dtype=np.float64).reshape(E)
+        n1 = n + 1
+
+        def coefficient(v):
+            if np.ndim(v) == 0:
+                return float(v)
+            a = np.asarray(v, dtype=np.float64)
+            return a.reshape(E) if a.size == E else a.reshape(E, n1, n1, n1)
+
+        self.kappa = coefficient(kappa)
+        self.c = coefficient(c)
+        self.kappa_pc = element_mean(self.gll, self.kappa) if np.ndim(self.kappa) == 4 else self.kappa
+        self.c_pc = element_mean(self.gll, self.c) if np.ndim(self.c) == 4 else self.c
         self._fine_on = fine
         self._coarse_on = coarse
         self.coarse_solver = coarse_solver
@@ -45,22 +57,26 @@ class Problem:
     def fine(self):
         if self._fine is None and self._fine_on:
             self._fine = FinePreconditioner(self.num, self.hexes, self.vtx, self.gll,
-                                            box_sizes(self.vtx, self.hexes), self.kappa, self.c)
+                                            box_sizes(self.vtx, self.hexes), self.kappa_pc, self.c_pc)
         return self._fine
 
     @property
     def coarse(self):
         if self._coarse is None and self._coarse_on:
             self._coarse = CoarseCorrection(self.num, self.geo, self.gll, self.vtx, self.hexes,
-                                            self.m, self.dirichlet, self.kappa, self.c, self.coarse_solver)
+                                            self.m, self.dirichlet, self.kappa_pc, self.c_pc, self.coarse_solver)
         return self._coarse
 
     def A(self, u):
         if np.all(np.asarray(self.kappa) == 1.0) and np.all(np.asarray(self.c) == 0.0):
             return apply_A(self.num, self.geo, self.gll, u, self.dirichlet)
         E = self.num.n_elem
+
+        def per_element_or_node(v):
+            return v if np.ndim(v) == 4 else np.broadcast_to(v, (E,))
+
         return apply_A(self.num, self.geo, self.gll, u, self.dirichlet,
-                       np.broadcast_to(self.kappa, (E,)), np.broadcast_to(self.c, (E,)))
+                       per_element_or_node(self.kappa), per_element_or_node(self.c))
 
     def precond(self, fine=True, coarse=True):
         return TwoScale(self.fine if fine else None, self.coarse if coarse else None,

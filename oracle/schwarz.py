@@ -230,6 +230,16 @@ def patch_table(num: Numbering, hexes, elements=None) -> np.ndarray:
     return out
 
 
+def element_mean(gll: GLL, v: np.ndarray) -> np.ndarray:
+    """One value per element of a coefficient given at the nodes v[e, k, j, i].
+
+    Reading: a patch solve (eq. (z)) and an order-1 coarse element (eq. (coarse))
+    use one kappa and one c; for a coefficient known per node they take its mean
+    over the reference cube by the GLL rule, (1/8) sum rho_i rho_j rho_k v_{ijk;e}."""
+    r = gll.rho
+    return np.einsum("ekji,k,j,i->e", v, r, r, r) / 8.0
+
+
 def fdm_patch_solve(S, lam, r_s, h, kappa=1.0, c=0.0):
     """eq. (z) for patches r_s[s, c, b, a] with box sizes h[s, 3] (step 4);
     kappa and c are constants or one value per patch."""

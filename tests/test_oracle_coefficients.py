@@ -15,7 +15,7 @@ from oracle.gll import GLL
 from oracle.neumann import face_mass
 from oracle.numbering import number_mesh
 from oracle.problem import Problem
-from oracle.schwarz import extended_pencil, fdm_basis, fdm_patch_solve
+from oracle.schwarz import element_mean, extended_pencil, fdm_basis, fdm_patch_solve
 
 
 def _per_element(E, seed=0):
@@ -100,3 +100,87 @@ def test_mixed_dirichlet_neumann_solution_converges():
         u, _, _, _ = P.solve(b, rtol=1e-13)
         errs.append(np.abs(u - meshgen.mixed_bc_u(x)).max())
     assert errs[1] < errs[0] / 20 and errs[1] <= 1e-5, errs
+
+
+# --- kappa and c per node (eq. (R) weights each quadrature point by its own kappa)
+
+def _per_node(E, n, seed=0):
+    rng = np.random.default_rng(seed)
+    shape = (E, n + 1, n + 1, n + 1)
+    return rng.uniform(0.2, 3.0, shape), rng.uniform(0.0, 5.0, shape)
+
+
+def test_operator_with_node_coefficients_equals_brute_force():
+    m = meshgen.cube_mesh(2, perturb=0.12, seed=14)
+    n = 3
+    kap, c = _per_node(len(m.hex), n, seed=3)
+    ng = number_mesh(m.hex, n).n_global
+    P = Problem(m.vtx, m.hex, n, fine=False, coarse=False, dirichlet=np.zeros(ng, np.uint8), kappa=kap, c=c)
+    A = _dense(m.vtx, m.hex, P.num.l2g, ng, P.gll, kap, c)
+    assert np.abs(A - A.T).max() <= 1e-13 * np.abs(A).max()
+    u = np.random.default_rng(1).uniform(-1, 1, ng)
+    assert np.linalg.norm(P.A(u) - A @ u) <= 1e-12 * np.linalg.norm(A @ u)
+
+
+@pytest.mark.parametrize("n", [2, 5])
+def test_coordinate_functions_under_node_kappa(n):
+    # x and y lie in the trilinear SEM space, so their gradients are exact at
+    # every quadrature point: y^T A x = sum_q w_q kappa_q (e_x . e_y) = 0 and
+    # x^T A x = sum of kappa times the local mass (no derivative matrices)
+    m = meshgen.cube_mesh((2, 3, 2), perturb=0.15, seed=15)
+    kap, _ = _per_node(len(m.hex), n, seed=4)
+    ng = number_mesh(m.hex, n).n_global
+    P = Problem(m.vtx, m.hex, n, fine=False, coarse=False, dirichlet=np.zeros(ng, np.uint8), kappa=kap)
+    ux, uy = P.x[:, 0].copy(), P.x[:, 1].copy()
+    Ax = P.A(ux)
+    energy = float(np.sum(kap * P.geo.mass))
+    assert abs(ux @ Ax - energy) <= 1e-12 * energy
+    assert abs(uy @ Ax) <= 1e-12 * energy
+
+
+def test_node_coefficients_constant_in_each_element_match_element_mode():
+    m = meshgen.cube_mesh(2, perturb=0.1, seed=16)
+    n = 4
+    E = len(m.hex)
+    kap, c = _per_element(E, seed=5)
+    full = (E, n + 1, n + 1, n + 1)
+    Pe = Problem(m.vtx, m.hex, n, kappa=kap, c=c)
+    Pn = Problem(m.vtx, m.hex, n, kappa=np.broadcast_to(kap[:, None, None, None], full).copy(),
+                 c=np.broadcast_to(c[:, None, None, None], full).copy())
+    u = np.random.default_rng(2).uniform(-1, 1, Pe.num.n_global)
+    ye, yn = Pe.A(u), Pn.A(u)
+    assert np.linalg.norm(ye - yn) <= 1e-13 * np.linalg.norm(ye)
+    ze, zn = Pe.precond()(u), Pn.precond()(u)
+    assert np.linalg.norm(ze - zn) <= 1e-13 * np.linalg.norm(ze)
+
+
+@pytest.mark.parametrize("n", [3, 6])
+def test_element_mean_is_exact_for_low_degree_polynomials(n):
+    # the GLL rule is exact to degree 2n - 1: the mean of
+    # 1 + xi^2 + eta^4 + zeta^3 over the reference cube is 1 + 1/3 + 1/5
+    g = GLL(n)
+    t = g.t
+    v = (1 + t[None, None, :] ** 2 + t[None, :, None] ** 4 + t[:, None, None] ** 3)[None]
+    v = np.concatenate([v, 2.5 * np.ones_like(v)])
+    assert np.allclose(element_mean(g, v), [1 + 1 / 3 + 1 / 5, 2.5], rtol=0, atol=1e-14)
+
+
+def test_variable_kappa_solution_converges():
+    # -div((1 + x) grad u) = s with u = sin(pi x) sin(pi y) sin(pi z):
+    # s = (1 + x) 3 pi^2 u - pi cos(pi x) sin(pi y) sin(pi z); kappa sampled at
+    # the nodes (a kappa dropped or applied after the derivative transpose errs by O(1))
+    errs = []
+    for n in (4, 6):
+        m = meshgen.cube_mesh(2, perturb=0.1, seed=17)
+        P0 = Problem(m.vtx, m.hex, n, fine=False, coarse=False)
+        xl = P0.x[P0.num.l2g]  # [E, k, j, i, 3]
+        P = Problem(m.vtx, m.hex, n, kappa=1.0 + xl[..., 0])
+        x = P.x
+        sx, sy, sz = (np.sin(np.pi * x[:, d]) for d in range(3))
+        u_ex = sx * sy * sz
+        s = (1.0 + x[:, 0]) * 3 * np.pi ** 2 * u_ex - np.pi * np.cos(np.pi * x[:, 0]) * sy * sz
+        b = P.m * s
+        b[P.dirichlet.astype(bool)] = 0.0
+        u, _, _, _ = P.solve(b, rtol=1e-13)
+        errs.append(np.abs(u - u_ex).max())
+    assert errs[1] < errs[0] / 20 and errs[1] <= 1e-4, errs
