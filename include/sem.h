@@ -194,7 +194,7 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
  * Errors: SEM_EINVAL (non-finite, kappa <= 0 or c < 0), SEM_ENOMEM, SEM_EHIP.
  */
 int sem_mesh_set_coefficients(sem_mesh m, double kappa, double c);
-/* Current constant (kappa, c) (host out); NaN while per-element values are in use. */
+/* Current constant (kappa, c) (host out); NaN while per-element or per-node values are in use. */
 int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c);
 
 /*
@@ -210,6 +210,25 @@ int sem_mesh_coefficients(sem_mesh m, double* kappa, double* c);
  * is changed), SEM_ENOMEM, SEM_EHIP.
  */
 int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa_host, const double* c_host);
+
+/*
+ * sem_mesh_set_node_coefficients -- kappa > 0 and c >= 0 at every local node
+ * (host arrays [n_hex][(N+1)^3] in input element order, local index
+ * i + (N+1) j + (N+1)^2 k; NULL: all 1, resp. all 0), as in eq. (R), where
+ * each quadrature point carries its own kappa: the six factors G at node
+ * (i,j,k) of element e are multiplied by kappa_{ijk;e} before the derivative
+ * transposes, and c_{ijk;e} m_{ijk;e} u_{ijk;e} is added before the gather.
+ * The device factors are replaced by the scaled ones (the host copy, and
+ * sem_mesh_geometry, keep the plain G; the operator kernel that rebuilds G
+ * from the vertices is not used while these are set).  The patch solves and
+ * the coarse matrix take one value per element: the mean over the reference
+ * cube by the GLL rule, (1/8) sum rho_i rho_j rho_k v_{ijk;e} (refactorised
+ * here; synchronises the device).  sem_mesh_set_coefficients and
+ * sem_mesh_set_element_coefficients restore the plain factors.
+ * Errors: SEM_EINVAL (a value non-finite, kappa <= 0 or c < 0; nothing is
+ * changed), SEM_ENOMEM, SEM_EHIP.
+ */
+int sem_mesh_set_node_coefficients(sem_mesh m, const double* kappa_host, const double* c_host);
 
 /*
  * sem_mesh_boundary_face_mass -- the Neumann term of eq. (pdeweak): for

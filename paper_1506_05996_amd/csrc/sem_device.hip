@@ -122,6 +122,20 @@ constexpr bool tile_ok(int epb) {
 template <typename T>
 OpCoef<T> op_coef(sem_mesh m) {
   OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr};
+  if (m->per_node) {  // kappa per node is inside G; c m per local node in place of the local mass
+    if constexpr (std::is_same<T, double>::value) {
+      oc.ke = m->nk64.p;
+      oc.ce = m->nc64.p;
+      oc.mL = m->nm64.p;
+    } else {
+      oc.ke = m->nk32.p;
+      oc.ce = m->nc32.p;
+      oc.mL = m->nm32.p;
+    }
+    if (oc.ke == nullptr || oc.ce == nullptr || (m->any_ce && oc.mL == nullptr))
+      throw Error{SEM_EINVAL, "per-node coefficients not on the device"};
+    return oc;
+  }
   if (m->per_elem) {  // per-element coefficients: applied by the element kernels
     if constexpr (std::is_same<T, double>::value) {
       oc.ke = m->ke64.p;
@@ -180,7 +194,11 @@ int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
       throw Error{SEM_EINVAL, "the matrix-core operator exists for FP64 at N = 15"};
     }
   }
-  if (epb == kTileGeo) return launch_ax_tile<N, T, ax_epb<N>(), true>(m, u, y, dpart, s);
+  if (epb == kTileGeo) {
+    // per-node kappa lives in the stored factors, which this kernel does not read
+    if (m->per_node) return launch_ax_tile<N, T, ax_epb<N>()>(m, u, y, dpart, s);
+    return launch_ax_tile<N, T, ax_epb<N>(), true>(m, u, y, dpart, s);
+  }
   switch (epb > 0 ? epb : ax_epb<N>()) {
     case 1: return launch_ax_tile<N, T, 1>(m, u, y, dpart, s);
     case 2: return launch_ax_tile<N, T, 2>(m, u, y, dpart, s);
@@ -895,11 +913,27 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
   return status;
 }
 
+// back from per-node coefficients: the plain factors G return to the device
+// (in place, so the buffers keep their addresses)
+void leave_node_coefficients(sem_mesh m) {
+  if (!m->per_node) return;
+  m->per_node = false;
+  if (m->host_only) return;
+  SEM_HIP(hipSetDevice(m->device));
+  SEM_HIP(hipDeviceSynchronize());
+  m->G64.copy_in(m->T.G.data(), m->T.G.size());
+  if (m->fp32) {
+    const std::vector<float> f = convert<float>(m->T.G);
+    m->G32.copy_in(f.data(), f.size());
+  }
+}
+
 // kappa and c of the operator, the patch solves and the coarse matrix (whose
 // values are reassembled and refactorised when they change)
 void set_coefficients(sem_mesh m, double kappa, double c) {
   HostTables& T = m->T;
   if (!m->per_elem && T.kappa == kappa && T.cmass == c) return;
+  leave_node_coefficients(m);
   T.kappa = kappa;
   T.cmass = c;
   T.kap_e.clear();
@@ -924,6 +958,7 @@ void set_coefficients(sem_mesh m, double kappa, double c) {
 void set_element_coefficients(sem_mesh m, const double* kap, const double* c) {
   HostTables& T = m->T;
   const int64_t E = T.E;
+  leave_node_coefficients(m);
   if (kap)
     T.kap_e.assign(kap, kap + E);
   else
@@ -953,6 +988,81 @@ void set_element_coefficients(sem_mesh m, const double* kap, const double* c) {
     if (m->fp32) {
       const std::vector<float> f = convert<float>(T.mass);
       m->mL32.upload(f.data(), f.size());
+    }
+  }
+  factor_coarse(m);
+}
+
+// kappa_{ijk;e} > 0 and c_{ijk;e} >= 0 at every local node (eq. (R)): kappa
+// multiplies the six factors G at its node, c the local mass.  The patch solves
+// and the coarse matrix take one value per element: the mean over the
+// reference cube by the GLL rule, (1/8) sum rho_i rho_j rho_k v_{ijk;e}.
+void set_node_coefficients(sem_mesh m, const double* kap, const double* c) {
+  HostTables& T = m->T;
+  const int64_t E = T.E;
+  const int n1 = T.n1;
+  const int64_t NN = (int64_t)n1 * n1 * n1;
+  T.kap_e.assign(E, 1.0);
+  T.c_e.assign(E, 0.0);
+  std::vector<double> nc(E, 0.0);
+  bool any_c = false;
+  for (int64_t e = 0; e < E; ++e) {
+    double ks = 0.0, cs = 0.0;
+    for (int k = 0; k < n1; ++k)
+      for (int j = 0; j < n1; ++j)
+        for (int i = 0; i < n1; ++i) {
+          const int64_t l = e * NN + i + (int64_t)n1 * (j + (int64_t)n1 * k);
+          const double w = T.rho[i] * T.rho[j] * T.rho[k] * 0.125;
+          if (kap) ks += w * kap[l];
+          if (c) {
+            cs += w * c[l];
+            if (c[l] != 0.0) nc[e] = 1.0;
+          }
+        }
+    if (kap) T.kap_e[e] = ks;
+    T.c_e[e] = cs;
+    any_c = any_c || nc[e] != 0.0;
+  }
+  T.kappa = T.cmass = std::nan("");
+  assemble_coarse_matrix(T);
+  m->per_elem = true;
+  m->per_node = true;
+  m->any_ce = any_c;
+  if (m->host_only) return;
+  SEM_HIP(hipSetDevice(m->device));
+  SEM_HIP(hipDeviceSynchronize());
+  // factors scaled by kappa at their node; c m per local node
+  std::vector<double> Gs(T.G.size());
+  for (int64_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f)
+      for (int64_t l = 0; l < NN; ++l) {
+        const int64_t o = (e * 6 + f) * NN + l;
+        Gs[o] = kap ? kap[e * NN + l] * T.G[o] : T.G[o];
+      }
+  std::vector<double> cm;
+  if (any_c) {
+    cm.resize((size_t)E * NN);
+    for (int64_t l = 0; l < E * NN; ++l) cm[l] = c[l] * T.mass[l];
+  }
+  const std::vector<double> ones(E, 1.0);
+  m->G64.copy_in(Gs.data(), Gs.size());
+  m->ke64.upload(T.kap_e.data(), E);
+  m->ce64.upload(T.c_e.data(), E);
+  m->nk64.upload(ones.data(), E);
+  m->nc64.upload(nc.data(), E);
+  if (any_c) m->nm64.upload(cm.data(), cm.size());
+  if (m->fp32) {
+    const std::vector<float> Gf = convert<float>(Gs);
+    m->G32.copy_in(Gf.data(), Gf.size());
+    const std::vector<float> kf = convert<float>(T.kap_e), cf = convert<float>(T.c_e);
+    m->ke32.upload(kf.data(), E);
+    m->ce32.upload(cf.data(), E);
+    const std::vector<float> of = convert<float>(ones), ncf = convert<float>(nc);
+    m->nk32.upload(of.data(), E);
+    m->nc32.upload(ncf.data(), E);
+    if (any_c) {
+      const std::vector<float> cmf = convert<float>(cm);
+      m->nm32.upload(cmf.data(), cmf.size());
     }
   }
   factor_coarse(m);
@@ -1511,6 +1621,19 @@ int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa, const dou
   }
   return guarded([&]() -> int {
     set_element_coefficients(m, kappa, c);
+    return SEM_OK;
+  });
+}
+
+int sem_mesh_set_node_coefficients(sem_mesh m, const double* kappa, const double* c) {
+  if (!m) return SEM_EINVAL;
+  const int64_t nl = m->T.n_local;
+  for (int64_t l = 0; l < nl; ++l) {
+    if (kappa && !(kappa[l] > 0.0 && std::isfinite(kappa[l]))) return SEM_EINVAL;
+    if (c && !(c[l] >= 0.0 && std::isfinite(c[l]))) return SEM_EINVAL;
+  }
+  return guarded([&]() -> int {
+    set_node_coefficients(m, kappa, c);
     return SEM_OK;
   });
 }

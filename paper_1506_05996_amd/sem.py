@@ -37,7 +37,7 @@ EXPORTS = [
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
-    "sem_mesh_set_element_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
+    "sem_mesh_set_element_coefficients", "sem_mesh_set_node_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
     "sem_mesh_amg_hierarchy",
 ]
 
@@ -89,6 +89,7 @@ _lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
 _lib.sem_mesh_set_coefficients.argtypes = [_p, ctypes.c_double, ctypes.c_double]
 _lib.sem_mesh_coefficients.argtypes = [_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.sem_mesh_set_element_coefficients.argtypes = [_p, _p, _p]
+_lib.sem_mesh_set_node_coefficients.argtypes = [_p, _p, _p]
 _lib.sem_mesh_boundary_face_mass.argtypes = [_p, _p, _i64, _p]
 _lib.sem_mesh_set_coarse_solver.argtypes = [_p, ctypes.c_int]
 _lib.sem_mesh_amg_hierarchy.argtypes = [_p, _p, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _p]
@@ -299,6 +300,23 @@ class Mesh:
                     raise ValueError(f"expected shape ({self.n_elem},), got {a.shape}")
                 arrs.append(a)
         _check(_lib.sem_mesh_set_element_coefficients(
+            self._h, *(a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs)))
+
+    def set_node_coefficients(self, kappa=None, c=None):
+        """kappa and c at every local node (arrays [n_elem, (N+1)^3] or
+        [n_elem, N+1, N+1, N+1] indexed [e, k, j, i]; None: 1 resp. 0)."""
+        import numpy as np
+        n1 = self.order + 1
+        arrs = []
+        for v in (kappa, c):
+            if v is None:
+                arrs.append(None)
+            else:
+                a = np.ascontiguousarray(v, dtype=np.float64)
+                if a.size != self.n_elem * n1 ** 3 or a.shape[0] != self.n_elem:
+                    raise ValueError(f"expected {self.n_elem} x {n1 ** 3} values, got shape {a.shape}")
+                arrs.append(a)
+        _check(_lib.sem_mesh_set_node_coefficients(
             self._h, *(a.ctypes.data_as(ctypes.c_void_p) if a is not None else None for a in arrs)))
 
     def boundary_face_mass(self, faces):

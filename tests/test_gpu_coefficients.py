@@ -1,6 +1,6 @@
-"""GPU parity with one kappa_e and c_e per element (Algorithm 2) and with a
-Neumann part of the boundary (eq. (pdeweak)), against the FP64 oracle through
-the C ABI.
+"""GPU parity with one kappa_e and c_e per element (Algorithm 2), with kappa
+and c at every node (eq. (R)) and with a Neumann part of the boundary
+(eq. (pdeweak)), against the FP64 oracle through the C ABI.
 
 Tolerances as for the Poisson path: FP64 operator, preconditioner and coarse
 solve 1e-12 relative L2; FP64 solutions 1e-10 (both sides solved to 1e-13).
@@ -76,6 +76,62 @@ def test_element_coefficients(name, kw, N):
     P0 = Problem(m.vtx, m.hex, N)
     y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
     assert rel_l2(y, P0.A(u)) <= 1e-12
+
+
+@pytest.mark.parametrize("name,kw,N", CASES, ids=[c[0] for c in CASES])
+def test_node_coefficients(name, kw, N):
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    print(f"[node coef case] {name}", flush=True)
+    m = meshgen.cube_mesh(**kw)
+    m, _ = meshgen.rotate_elements(m, seed=49)
+    m, _ = meshgen.permute_elements(m, seed=50)
+    E = len(m.hex)
+    rng = np.random.default_rng(31)
+    shape = (E, N + 1, N + 1, N + 1)
+    kap, c = rng.uniform(0.2, 3.0, shape), rng.uniform(0.0, 5.0, shape)
+    c[: E // 2] = 0.0  # elements without a mass term beside elements with one
+    M = sem.Mesh(m.vtx, m.hex, N)
+    G0, _ = M.geometry()
+    P = Problem(m.vtx, m.hex, N, kappa=kap, c=c)
+    M.set_node_coefficients(kap, c)
+    assert np.isnan(M.coefficients()).all()
+    assert np.array_equal(M.geometry()[0], G0)  # the host keeps the plain factors
+    u = rng.uniform(-1, 1, M.n_global)
+    yo = P.A(u)
+    tiles = [None] + ([sem.TILE_GEO] if N <= 9 else []) + ([16] if N == 15 else [])
+    for tile in tiles:
+        if tile is not None:
+            M.set_tile(tile)
+        y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
+        assert rel_l2(y, yo) <= 1e-12, tile
+    y32 = M.apply_A(torch.tensor(u, device=dev, dtype=torch.float32)).double().cpu().numpy()
+    assert rel_l2(y32, yo) <= 1e-5
+    r = rng.uniform(-1, 1, M.n_global)
+    r[P.num.dirichlet.astype(bool)] = 0.0
+    for pc in (1, 2, 3):
+        z = M.precond(torch.tensor(r, device=dev), pc=pc).cpu().numpy()
+        assert rel_l2(z, P.precond(fine=bool(pc & 1), coarse=bool(pc & 2))(r)) <= 1e-12, pc
+    b = P.load(lambda x: meshgen.manufactured_s(x, m.lengths))
+    ut, _, _, _ = P.solve(b, rtol=1e-13)
+    x, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    assert rel_l2(x.cpu().numpy(), ut) <= 1e-10
+    x, info = M.solve(torch.tensor(b, device=dev), mode=sem.SOLVE_FP32_REFINED, rtol=1e-12)
+    assert rel_l2(x.cpu().numpy(), ut) <= 1e-9
+    # back to constant, then per-element coefficients: the plain factors are
+    # on the device again (also for the kernel that rebuilds them)
+    M.set_coefficients(1.0, 0.0)
+    P0 = Problem(m.vtx, m.hex, N)
+    for tile in tiles:
+        if tile is not None:
+            M.set_tile(tile)
+        y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
+        assert rel_l2(y, P0.A(u)) <= 1e-12, tile
+    ke = rng.uniform(0.5, 2.0, E)
+    M.set_node_coefficients(kap)
+    M.set_element_coefficients(ke)
+    y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
+    assert rel_l2(y, Problem(m.vtx, m.hex, N, fine=False, coarse=False, kappa=ke).A(u)) <= 1e-12
 
 
 @pytest.mark.parametrize("N", [4, 6])

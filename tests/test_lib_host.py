@@ -143,6 +143,33 @@ def test_coefficients_on_a_host_handle():
     assert st == sem.SEM_EUNSUPPORTED
 
 
+def test_node_coefficients_on_a_host_handle():
+    # per-node kappa and c are validated (nothing changes on a bad value) and
+    # the constant coefficients read NaN while they are in use
+    m = meshgen.cube_mesh(2, perturb=0.1)
+    N = 3
+    M = sem.Mesh(m.vtx, m.hex, N, host_only=True)
+    shape = (len(m.hex), (N + 1) ** 3)
+    kap = np.full(shape, 2.0)
+    for bad in (0.0, -1.0, float("nan"), float("inf")):
+        k = kap.copy()
+        k[3, 5] = bad
+        with pytest.raises(sem.SemError) as e:
+            M.set_node_coefficients(k)
+        assert e.value.status == sem.SEM_EINVAL
+        assert M.coefficients() == (1.0, 0.0)
+    c = np.zeros(shape)
+    c[1, 2] = -0.5
+    with pytest.raises(sem.SemError):
+        M.set_node_coefficients(kap, c)
+    with pytest.raises(ValueError):
+        M.set_node_coefficients(kap[:, :-1])
+    M.set_node_coefficients(kap, np.abs(c))
+    assert np.isnan(M.coefficients()).all()
+    M.set_coefficients(1.0, 0.0)
+    assert M.coefficients() == (1.0, 0.0)
+
+
 def test_boundary_face_mass_matches_oracle():
     from oracle.gll import GLL
     from oracle.neumann import face_mass
