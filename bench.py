@@ -458,7 +458,7 @@ def main():
         achieved = falg / (ms_elem * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFS, 4),
-                    "traffic": traffic_from_counters("ax_kernel<7, double, 1, true>"),
+                    "traffic": traffic_from_counters("ax_kernel<7, double, 1, true, false>"),
                     "kernel": "ax_kernel, factors rebuilt from the element vertices (tile %d)" % tile,
                     "ms_ax_kernel": round(ms_elem, 4), "ms_gs_kernel": round(ms_gs, 4),
                     "algorithmic_flops": falg}
@@ -466,7 +466,7 @@ def main():
         achieved = balg / ((ms_elem + ms_gs) * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_from_counters("ax_kernel<7, double, %d, false>" % tile),
+                    "traffic": traffic_from_counters("ax_kernel<7, double, %d, false, false>" % tile),
                     "kernel": "sem_apply_A = ax_kernel (stored factors, tile %d) + gs_kernel" % tile,
                     "ms_ax_kernel": round(ms_elem, 4), "ms_gs_kernel": round(ms_gs, 4),
                     "algorithmic_bytes": balg}

@@ -219,8 +219,9 @@ int sem_mesh_set_element_coefficients(sem_mesh m, const double* kappa_host, cons
  * (i,j,k) of element e are multiplied by kappa_{ijk;e} before the derivative
  * transposes, and c_{ijk;e} m_{ijk;e} u_{ijk;e} is added before the gather.
  * The device factors are replaced by the scaled ones (the host copy, and
- * sem_mesh_geometry, keep the plain G; the operator kernel that rebuilds G
- * from the vertices is not used while these are set).  The patch solves and
+ * sem_mesh_geometry, keep the plain G), and the operator kernel that rebuilds
+ * G from the vertices reads kappa per local node (an [n_hex][(N+1)^3] copy on
+ * the device, FP64 and FP32).  The patch solves and
  * the coarse matrix take one value per element: the mean over the reference
  * cube by the GLL rule, (1/8) sum rho_i rho_j rho_k v_{ijk;e} (refactorised
  * here; synchronises the device).  sem_mesh_set_coefficients and

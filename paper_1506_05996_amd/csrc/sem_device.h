@@ -102,13 +102,14 @@ struct sem_mesh_s {
   DBuf<double> ke64, ce64, mL64;
   DBuf<float> ke32, ce32, mL32;
   // per-node coefficients: kappa_{ijk;e} is folded into the device factors G
-  // (the host keeps the plain G), the element kernels take kappa_e = 1 (nk),
-  // c_e = 1 where the element has some c != 0 (nc) and c_{ijk;e} m_{ijk;e} in
-  // place of the local mass (nm); ke/ce then hold the element means that the
-  // patch solves and the coarse matrix use (per_elem is set too)
+  // (the host keeps the plain G) and kept per local node (kn) for the kernel
+  // that rebuilds G; the element kernels take kappa_e = 1 (nk), c_e = 1 where
+  // the element has some c != 0 (nc) and c_{ijk;e} m_{ijk;e} in place of the
+  // local mass (nm); ke/ce then hold the element means that the patch solves
+  // and the coarse matrix use (per_elem is set too)
   bool per_node = false;
-  DBuf<double> nk64, nc64, nm64;
-  DBuf<float> nk32, nc32, nm32;
+  DBuf<double> nk64, nc64, nm64, kn64;
+  DBuf<float> nk32, nc32, nm32, kn32;
   // coarse solver: 0 exact (nested dissection), 1 aggregation AMG with a K-cycle
   int coarse_solver = 0;
   struct AmgDev {

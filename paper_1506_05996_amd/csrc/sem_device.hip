@@ -121,18 +121,20 @@ constexpr bool tile_ok(int epb) {
 // coefficients of the operator for dtype T (kappa = 1, c = 0 unless set)
 template <typename T>
 OpCoef<T> op_coef(sem_mesh m) {
-  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr};
-  if (m->per_node) {  // kappa per node is inside G; c m per local node in place of the local mass
+  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  if (m->per_node) {  // kappa per node is inside the stored G (kn: for the rebuilt G); c m per local node
     if constexpr (std::is_same<T, double>::value) {
       oc.ke = m->nk64.p;
       oc.ce = m->nc64.p;
       oc.mL = m->nm64.p;
+      oc.kn = m->kn64.p;
     } else {
       oc.ke = m->nk32.p;
       oc.ce = m->nc32.p;
       oc.mL = m->nm32.p;
+      oc.kn = m->kn32.p;
     }
-    if (oc.ke == nullptr || oc.ce == nullptr || (m->any_ce && oc.mL == nullptr))
+    if (oc.ke == nullptr || oc.ce == nullptr || oc.kn == nullptr || (m->any_ce && oc.mL == nullptr))
       throw Error{SEM_EINVAL, "per-node coefficients not on the device"};
     return oc;
   }
@@ -164,12 +166,12 @@ OpCoef<T> op_coef(sem_mesh m) {
 // element kernel launches; with dpart, each workgroup also leaves its share
 // of u . y over the element interiors in dpart[block] (the grid size is
 // returned so the caller knows how many)
-template <int N, typename T, int EPB, bool GEO = false>
+template <int N, typename T, int EPB, bool GEO = false, bool KN = false>
 int64_t launch_ax_tile(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   if constexpr (tile_ok<N>(EPB)) {
     const HostTables& T_ = m->T;
     const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
-    hipLaunchKernelGGL((ax_kernel<N, T, EPB, GEO>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u,
+    hipLaunchKernelGGL((ax_kernel<N, T, EPB, GEO, KN>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s, u,
                        y, Wp<T>(m), GEO ? X8p<T>(m) : Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart,
                        TQp<T>(m), op_coef<T>(m));
     SEM_HIP(hipGetLastError());
@@ -195,8 +197,8 @@ int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
     }
   }
   if (epb == kTileGeo) {
-    // per-node kappa lives in the stored factors, which this kernel does not read
-    if (m->per_node) return launch_ax_tile<N, T, ax_epb<N>()>(m, u, y, dpart, s);
+    // per-node kappa: read per node by its own instance of the kernel
+    if (m->per_node) return launch_ax_tile<N, T, ax_epb<N>(), true, true>(m, u, y, dpart, s);
     return launch_ax_tile<N, T, ax_epb<N>(), true>(m, u, y, dpart, s);
   }
   switch (epb > 0 ? epb : ax_epb<N>()) {
@@ -227,7 +229,7 @@ int64_t launch_gs(sem_mesh m, T* y, hipStream_t s, const T* pd = nullptr, double
                   const T* u_op = nullptr) {
   const HostTables& T_ = m->T;
   const int64_t grid = blocks_for(T_.base_i);
-  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr};
+  OpCoef<T> oc{T(1), T(0), nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   if (u_op != nullptr && !m->per_elem) oc = op_coef<T>(m);
   hipLaunchKernelGGL((gs_kernel<T>), dim3((unsigned)grid), dim3(kGS), 0, s, y, Wp<T>(m), m->vinc_off.p,
                      m->einc_off.p, m->fcount.p, m->dir.p, T_.V, T_.base_f, T_.base_i, T_.N - 1, T_.wedge_off,
@@ -1046,6 +1048,13 @@ void set_node_coefficients(sem_mesh m, const double* kap, const double* c) {
   }
   const std::vector<double> ones(E, 1.0);
   m->G64.copy_in(Gs.data(), Gs.size());
+  // kappa per node for the operator kernel that rebuilds G from the vertices
+  std::vector<double> kl;
+  if (kap)
+    kl.assign(kap, kap + E * NN);
+  else
+    kl.assign((size_t)E * NN, 1.0);
+  m->kn64.upload(kl.data(), kl.size());
   m->ke64.upload(T.kap_e.data(), E);
   m->ce64.upload(T.c_e.data(), E);
   m->nk64.upload(ones.data(), E);
@@ -1054,6 +1063,8 @@ void set_node_coefficients(sem_mesh m, const double* kap, const double* c) {
   if (m->fp32) {
     const std::vector<float> Gf = convert<float>(Gs);
     m->G32.copy_in(Gf.data(), Gf.size());
+    const std::vector<float> klf = convert<float>(kl);
+    m->kn32.upload(klf.data(), klf.size());
     const std::vector<float> kf = convert<float>(T.kap_e), cf = convert<float>(T.c_e);
     m->ke32.upload(kf.data(), E);
     m->ce32.upload(cf.data(), E);

@@ -39,6 +39,8 @@ struct OpCoef {
   const T* ke;  // per element: kappa_e [E] (NULL: constant coefficients)
   const T* ce;  // per element: c_e [E]
   const T* mL;  // per element: local mass m_{ijk;e} [E][(N+1)^3], read where c_e != 0
+  const T* kn;  // per node: kappa_{ijk;e} [E][(N+1)^3], read by the kernel that rebuilds G
+                // (the stored factors carry kappa already); NULL otherwise
 };
 
 template <typename T>
@@ -149,6 +151,8 @@ inline int64_t xcd_grid(int64_t nlogical) { return ((nlogical + 7) / 8) * 8; }
 // G_ab = rho_i rho_j rho_k (a_a . a_b) / det J with det J = c0 . a0, the same
 // rho rho rho |J| (J^T J)^-1 as the stored factors.  In that case G points to
 // the vertex coordinates [E][8][3] and tq to the GLL points and weights [2][N+1].
+// KN (with GEO): kappa per node (oc.kn) scales the rebuilt factors at its node;
+// the element's values are staged in LDS next to u.
 // 1/d for a positive, normal d: hardware reciprocal refined by Newton steps
 // (two in FP64, one in FP32): within about an ulp of the rounded quotient
 __device__ __forceinline__ double recip_pos(double d) {
@@ -162,7 +166,7 @@ __device__ __forceinline__ float recip_pos(float d) {
   return __builtin_fmaf(y, __builtin_fmaf(-d, y, 1.0f), y);
 }
 
-template <int N, typename T, int EPB, bool GEO = false>
+template <int N, typename T, int EPB, bool GEO = false, bool KN = false>
 __global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
 __attribute__((amdgpu_waves_per_eu(N <= 9 ? (GEO && sizeof(T) == 8 ? 3 : 4) : 1, 8)))
 ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
@@ -175,6 +179,7 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   __shared__ T sU[EPB][NN];  // the element's gathered u, all planes
   __shared__ T sA[EPB][P];
   __shared__ T sB[EPB][P];
+  __shared__ T sK[KN ? EPB : 1][KN ? NN : 1];  // KN: the element's kappa per node
   const int tid = threadIdx.x;
   const int le = tid / P, ij = tid - le * P;
   const int i = ij % n1, j = ij / n1;
@@ -232,6 +237,10 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       sU[le][k * P + ij] = valid ? uv[k] : T(0);
       rw[k] = T(0);
     }
+    if constexpr (KN) {
+#pragma unroll
+      for (int k = 0; k < n1; ++k) sK[le][k * P + ij] = valid ? oc.kn[e * NN + k * P + ij] : T(1);
+    }
   }
   __syncthreads();
   // FP64 rebuilt-factor form: the lane's two columns of D stay in registers
@@ -262,7 +271,8 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
       const T a1x = C2[1] * c0[2] - C2[2] * c0[1], a1y = C2[2] * c0[0] - C2[0] * c0[2], a1z = C2[0] * c0[1] - C2[1] * c0[0];
       const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
       const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
-      const T sc = rij * tq[n1 + k] * recip_pos(det);
+      T sc = rij * tq[n1 + k] * recip_pos(det);
+      if constexpr (KN) sc *= sK[le][k * P + ij];  // kappa at the node (eq. (R))
       g0 = sc * (a0x * a0x + a0y * a0y + a0z * a0z);
       g1 = sc * (a0x * a1x + a0y * a1y + a0z * a1z);
       g2 = sc * (a0x * a2x + a0y * a2y + a0z * a2z);
