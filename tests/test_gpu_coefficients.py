@@ -137,6 +137,37 @@ def test_node_coefficients(name, kw, N):
     assert rel_l2(y, Problem(m.vtx, m.hex, N, fine=False, coarse=False, kappa=ke).A(u)) <= 1e-12
 
 
+def test_node_mass_term_only_with_a_changed_dirichlet_set():
+    # c per node with kappa left at 1, then a Dirichlet set with a free face:
+    # the coarse matrix is refactorised with the element means of c
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(3, perturb=0.1, seed=21)
+    m, _ = meshgen.rotate_elements(m, seed=51)
+    N = 4
+    E = len(m.hex)
+    c = np.random.default_rng(32).uniform(0.0, 8.0, (E, N + 1, N + 1, N + 1))
+    M = sem.Mesh(m.vtx, m.hex, N)
+    M.set_node_coefficients(None, c)
+    x = M.node_coords()
+    dirichlet = (M.boundary_mask().astype(bool) & ~(np.abs(x[:, 2] - 1.0) <= 1e-12)).astype(np.uint8)
+    M.set_dirichlet(dirichlet)
+    P = Problem(m.vtx, m.hex, N, dirichlet=dirichlet, c=c)
+    rng = np.random.default_rng(33)
+    u = rng.uniform(-1, 1, M.n_global)
+    assert rel_l2(M.apply_A(torch.tensor(u, device=dev)).cpu().numpy(), P.A(u)) <= 1e-12
+    r = rng.uniform(-1, 1, M.n_global)
+    r[dirichlet.astype(bool)] = 0.0
+    z = M.precond(torch.tensor(r, device=dev)).cpu().numpy()
+    assert rel_l2(z, P.precond()(r)) <= 1e-12
+    b = P.m * np.cos(x[:, 0])
+    b[dirichlet.astype(bool)] = 0.0
+    ut, it_o, _, _ = P.solve(b, rtol=1e-13)
+    xs, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    assert rel_l2(xs.cpu().numpy(), ut) <= 1e-10
+    assert abs(info["iterations"] - it_o) <= 2
+
+
 @pytest.mark.parametrize("N", [4, 6])
 def test_mixed_dirichlet_neumann_solve(N):
     from paper_1506_05996_amd import sem
