@@ -812,7 +812,7 @@ __global__ void __launch_bounds__((N + 1) * (N + 1))
 restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t* __restrict__ rec,
                 const double* __restrict__ phi, const int32_t* __restrict__ order, int64_t E) {
   constexpr int n1 = N + 1, P = n1 * n1;
-  __shared__ double red[8][P];
+  __shared__ double red[8][P + 1];  // padded: the eight summing lanes read eight distinct banks
   __shared__ double sPhi[2 * n1];
   const int tid = threadIdx.x;
   const int i = tid % n1, j = tid / n1;
@@ -872,8 +872,19 @@ restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, co
   if (v >= V) return;
   const int32_t c = cidx[v];
   if (c < 0) return;
+  // four incidences in flight at a time; the sum still runs in list order
+  const int32_t q1 = vinc_off[v + 1];
+  int32_t q = vinc_off[v];
   double s = 0.0;
-  for (int32_t q = vinc_off[v]; q < vinc_off[v + 1]; ++q) s += Re[vinc_ec[q]];
+  for (; q + 4 <= q1; q += 4) {
+    const int32_t a0 = vinc_ec[q], a1 = vinc_ec[q + 1], a2 = vinc_ec[q + 2], a3 = vinc_ec[q + 3];
+    const double b0 = Re[a0], b1 = Re[a1], b2 = Re[a2], b3 = Re[a3];
+    s += b0;
+    s += b1;
+    s += b2;
+    s += b3;
+  }
+  for (; q < q1; ++q) s += Re[vinc_ec[q]];
   R[c] = s;
 }
 
