@@ -64,6 +64,41 @@ def algorithmic_flops_ax(n_local, N, geometry_on_the_fly):
     return n_local * (12 * (N + 1) + 18 + (104 if geometry_on_the_fly else 0))
 
 
+def pcg_iteration_bytes(E, N, n_local, n_global, coarse_entries, s):
+    """Algorithmic HBM bytes of one PCG iteration as the path runs it, with the
+    fine-level vectors in s-byte floats and the coarse factor in FP64: the
+    operator with the factors rebuilt from the vertices (input gather and
+    entity records per local node, 24 vertex doubles per element, the gather
+    of the shared nodes), the patch solves (index, residual gather and
+    correction per patch node, an index per outside slot), the sum of the
+    corrections with the shared-node gather, the restriction, both coarse
+    sweeps, and the r and p/x vector updates."""
+    patch = E * (N + 3) ** 3
+    outside = E * ((N + 3) ** 3 - (N + 1) ** 3)
+    shared = n_local - E * (N - 1) ** 3
+    op = n_local * (s + 4) + 192 * E + 2 * s * n_global
+    fine = patch * (4 + 2 * s) + 4 * outside
+    assemble = s * patch + s * n_local + 2 * s * shared
+    coarse = s * n_local + 64 * E + 8 * coarse_entries
+    vectors = 3 * s * n_global + 5 * s * n_global
+    return op + fine + assemble + coarse + vectors
+
+
+def pcg_roofline(E, N, n_local, n_global, coarse_entries, info, time_s, refined):
+    """Time-to-tolerance against the HBM roofline: the iterations' algorithmic
+    bytes at the 8 TB/s peak over the measured solve time."""
+    if refined:
+        inner = info["iterations"] * pcg_iteration_bytes(E, N, n_local, n_global, coarse_entries, 4)
+        # each outer step: FP64 operator, true residual, scaling to FP32, FP64 update of x
+        outer = (info["outer"] + 1) * (n_local * 12 + 192 * E + 16 * n_global + 56 * n_global)
+        total = inner + outer
+    else:
+        total = info["iterations"] * pcg_iteration_bytes(E, N, n_local, n_global, coarse_entries, 8)
+    floor_s = total / (HBM_PEAK_GBS * 1e9)
+    return {"bound": "hbm", "algorithmic_bytes": int(total), "floor_s": round(floor_s, 4),
+            "frac": round(floor_s / time_s, 4)}
+
+
 def traffic_from_counters(kernel):
     """HBM bytes per apply from committed rocprofv3 counter runs, when they
     were taken on the current kernel source for this element kernel; else None."""
@@ -520,6 +555,8 @@ def main():
             pcg[name] = {"time_s": round(float(np.median(times)), 4), "iterations": info["iterations"],
                          "outer": info["outer"], "true_rel_residual": res, "err_max_vs_exact": emax,
                          "err_l2m_vs_exact": el2, "reps": len(times)}
+            pcg[name]["roofline"] = pcg_roofline(mesh.n_elem, N, nl, ng, sum(M.coarse_factor_size()), info,
+                                                 pcg[name]["time_s"], mode == sem.SOLVE_FP32_REFINED)
             log(f"[bench] PCG {name}: {pcg[name]}")
         pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
         if not args.no_amg:

@@ -332,6 +332,13 @@ int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int 
 int sem_mesh_tile(sem_mesh m, int dtype, int* epb);
 int sem_mesh_set_tile(sem_mesh m, int dtype, int epb);
 
+/* Entries of the coarse factor that one exact coarse solve of Section 4.1
+   reads: *fwd_entries of the stacked blocks [S^-1; W] of the nested-
+   dissection fronts (forward sweep), *bwd_entries of the blocks W^T (backward
+   sweep), FP64 each; both 0 before the first factorisation.  For byte counts
+   (roofline of an iteration); SEM_EINVAL on a NULL argument. */
+int sem_mesh_coarse_factor_size(sem_mesh m, int64_t* fwd_entries, int64_t* bwd_entries);
+
 const char* sem_last_error(void);
 
 #ifdef __cplusplus

@@ -1377,6 +1377,13 @@ int sem_mesh_tile(sem_mesh m, int dtype, int* epb) {
   return SEM_OK;
 }
 
+int sem_mesh_coarse_factor_size(sem_mesh m, int64_t* fwd_entries, int64_t* bwd_entries) {
+  if (!m || !fwd_entries || !bwd_entries) return SEM_EINVAL;
+  *fwd_entries = m->T.fwd_size;
+  *bwd_entries = m->T.bwd_size;
+  return SEM_OK;
+}
+
 void sem_default_solve_opts(sem_solve_opts* o) {
   if (!o) return;
   o->mode = SEM_SOLVE_FP64;

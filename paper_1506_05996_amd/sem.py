@@ -35,7 +35,7 @@ EXPORTS = [
     "sem_mesh_sizes", "sem_mesh_numbering", "sem_mesh_gs_csr", "sem_mesh_patch_table",
     "sem_mesh_node_coords", "sem_mesh_lumped_mass", "sem_mesh_boundary_mask", "sem_mesh_geometry",
     "sem_mesh_set_dirichlet", "sem_apply_A", "sem_precond", "sem_coarse_solve", "sem_pcg_solve",
-    "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
+    "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_mesh_coarse_factor_size", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
     "sem_mesh_set_element_coefficients", "sem_mesh_set_node_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
     "sem_mesh_amg_hierarchy",
@@ -86,6 +86,7 @@ _lib.sem_batch_sizes.argtypes = [_p, _p]
 _lib.sem_batch_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), _p, _p]
 _lib.sem_batch_destroy.argtypes = [_p]
 _lib.sem_mesh_tile.argtypes = [_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+_lib.sem_mesh_coarse_factor_size.argtypes = [_p, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]
 _lib.sem_mesh_set_coefficients.argtypes = [_p, ctypes.c_double, ctypes.c_double]
 _lib.sem_mesh_coefficients.argtypes = [_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.sem_mesh_set_element_coefficients.argtypes = [_p, _p, _p]
@@ -252,6 +253,12 @@ class Mesh:
         v = ctypes.c_int()
         _check(_lib.sem_mesh_tile(self._h, int(dtype), ctypes.byref(v)))
         return v.value
+
+    def coarse_factor_size(self):
+        """(forward, backward) FP64 entries one exact coarse solve reads."""
+        f, b = _i64(), _i64()
+        _check(_lib.sem_mesh_coarse_factor_size(self._h, ctypes.byref(f), ctypes.byref(b)))
+        return f.value, b.value
 
     def set_tile(self, epb, dtype=SEM_F64):
         _check(_lib.sem_mesh_set_tile(self._h, int(dtype), int(epb)))

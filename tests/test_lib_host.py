@@ -272,3 +272,19 @@ def test_coarse_solver_selection_on_a_host_handle():
         assert e.value.status == sem.SEM_EINVAL
     sizes, agg0 = M.amg_hierarchy()
     assert list(sizes) == [1] and agg0 is None  # one free vertex: the coarsest level at once
+
+
+@pytest.mark.parametrize("k", [2, 3, 6])
+def test_coarse_factor_size_bounds(k):
+    """The nested-dissection fronts partition the free coarse vertices: their
+    own blocks (sum of s^2 = forward minus backward entries) hold at least one
+    entry per free vertex and at most a dense factor's n_c^2; a single interior
+    vertex is one 1x1 front with no boundary."""
+    m = meshgen.cube_mesh(k, perturb=0.1)
+    M = sem.Mesh(m.vtx, m.hex, 2, host_only=True)
+    fwd, bwd = M.coarse_factor_size()
+    nc = (k - 1) ** 3
+    assert bwd >= 0
+    assert nc <= fwd - bwd <= nc * nc
+    if k == 2:
+        assert (fwd, bwd) == (1, 0)
