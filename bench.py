@@ -555,13 +555,17 @@ def main():
             pcg[name] = {"time_s": round(float(np.median(times)), 4), "iterations": info["iterations"],
                          "outer": info["outer"], "true_rel_residual": res, "err_max_vs_exact": emax,
                          "err_l2m_vs_exact": el2, "reps": len(times)}
+            if mode == sem.SOLVE_FP64:
+                x64 = x.clone()
+            else:
+                pcg[name]["rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
             pcg[name]["roofline"] = pcg_roofline(mesh.n_elem, N, nl, ng, sum(M.coarse_factor_size()), info,
                                                  pcg[name]["time_s"], mode == sem.SOLVE_FP32_REFINED)
             log(f"[bench] PCG {name}: {pcg[name]}")
         pcg["speedup_fp32_refined"] = round(pcg["fp64"]["time_s"] / pcg["fp32_refined"]["time_s"], 3)
         if not args.no_amg:
             pcg["amg_coarse_solver"] = run_amg(M, b, dev, args)
-        del b, ue_d, mN
+        del b, ue_d, mN, x64
 
     coefs = None
     if not args.no_coef:
