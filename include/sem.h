@@ -324,7 +324,7 @@ int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int 
 
 /* Tile of the operator kernel for dtype: elements per workgroup (1, 2, 4, 8;
    (N+1)^2 lanes each, at most 1024 lanes), 16 for the matrix-core kernel
-   (FP64 at N = 15 only), or 32 for the kernel that rebuilds the geometric
+   (N = 15 only, FP64 or FP32), or 32 for the kernel that rebuilds the geometric
    factors at every node from the element's 8 vertices instead of reading them
    (Section 3; same factors up to rounding).  Chosen by the autotuner or the
    default for the order; sem_mesh_set_tile overrides it (SEM_EINVAL if not

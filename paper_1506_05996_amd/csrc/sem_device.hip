@@ -107,7 +107,7 @@ const float* CEp<float>(sem_mesh m) { return m->ce32.p; }
 
 // --- operator ---------------------------------------------------------------
 // tile candidates: elements per workgroup, workgroups of at most 1024 lanes;
-// kTileMfma selects the matrix-core kernel (FP64, N = 15), kTileGeo the kernel
+// kTileMfma selects the matrix-core kernel (N = 15), kTileGeo the kernel
 // that rebuilds the geometric factors from the vertices
 constexpr int kTileCandidates[4] = {1, 2, 4, 8};
 constexpr int kTileMfma = 16;
@@ -185,15 +185,15 @@ template <int N, typename T>
 int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   const int epb = m->epb[std::is_same<T, double>::value ? 0 : 1];
   if (epb == kTileMfma) {
-    if constexpr (N == 15 && std::is_same<T, double>::value) {
+    if constexpr (N == 15) {
       const HostTables& T_ = m->T;
       const int64_t grid = xcd_grid(T_.E);
-      hipLaunchKernelGGL(ax_mfma15_kernel, dim3((unsigned)grid), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
-                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart, op_coef<double>(m));
+      hipLaunchKernelGGL((ax_mfma15_kernel<T>), dim3((unsigned)grid), dim3(256), 0, s, u, y, Wp<T>(m), Gp<T>(m),
+                         m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart, op_coef<T>(m));
       SEM_HIP(hipGetLastError());
       return grid;
     } else {
-      throw Error{SEM_EINVAL, "the matrix-core operator exists for FP64 at N = 15"};
+      throw Error{SEM_EINVAL, "the matrix-core operator exists at N = 15"};
     }
   }
   if (epb == kTileGeo) {
@@ -1234,7 +1234,7 @@ int tune_tile(sem_mesh m) {
   std::vector<int> cands;
   for (int c : kTileCandidates)
     if (c * (N + 1) * (N + 1) <= 1024 && c * (N + 1) * (N + 1) >= 16) cands.push_back(c);
-  if (N == 15 && std::is_same<T, double>::value) cands.push_back(kTileMfma);
+  if (N == 15) cands.push_back(kTileMfma);
   cands.push_back(kTileGeo);
   if (cands.size() <= 1) return cands.empty() ? 1 : cands[0];
   DBuf<T> u, y;
@@ -1299,7 +1299,7 @@ void autotune(sem_mesh m, const char* cache) {
       }
     }
     if (found == 1 || found == 2 || found == 4 || found == 8 || found == kTileGeo ||
-        (found == kTileMfma && d == 0 && m->T.N == 15)) {
+        (found == kTileMfma && m->T.N == 15)) {
       m->epb[d] = found;
       continue;
     }
@@ -1362,7 +1362,7 @@ int sem_mesh_set_tile(sem_mesh m, int dtype, int epb) {
   const int N = m->T.N;
   const bool ok = (epb == 1 || epb == 2 || epb == 4 || epb == 8)
                       ? epb * (N + 1) * (N + 1) <= 1024
-                      : (epb == kTileGeo || (epb == kTileMfma && N == 15 && dtype == SEM_F64));
+                      : (epb == kTileGeo || (epb == kTileMfma && N == 15));
   if (!ok) {
     set_error("tile not available for this order and dtype");
     return SEM_EINVAL;

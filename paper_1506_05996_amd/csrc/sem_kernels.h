@@ -360,29 +360,47 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
 }
 
 // ---------------------------------------------------------------------------
-// Operator at N = 15 on FP64 matrix cores (v_mfma_f64_16x16x4f64).  One
+// Operator at N = 15 on matrix cores (v_mfma_f64_16x16x4f64 in FP64,
+// v_mfma_f32_16x16x4_f32 in FP32: the same operand layout).  One
 // workgroup of four waves per element (16^3 nodes).  MFMA operand layout for
 // a 16x16 product with K = 4: lane l supplies A[l%16][l/16] and B[l/16][l%16]
-// and receives D[4r + l/16][l%16] in accumulator register r = 0..3.
+// and receives D[4r + l/16][l%16] (FP64) or D[4(l/16) + r][l%16] (FP32) in
+// accumulator register r = 0..3.
 //   1. zeta derivative  UT = D (16x16) x U (16 x 256 columns (j,i)), 4 tiles per wave
 //   2. per plane k (4 planes per wave): UR = U_k D^T, US = D U_k, the factors
 //      G at the lane's 4 nodes, A, B, C; then W_k = A_k D + D^T B_k
 //   3. zeta transpose  W += D^T (16x16) x C (16 x 256), 4 tiles per wave, and the
 //      results go to y (element interiors) or the work array (shared nodes).
-// D is held in registers in both operand layouts (4 + 4 doubles per lane).
+// D is held in registers in both operand layouts (4 + 4 values per lane).
 typedef double sem_d4 __attribute__((ext_vector_type(4)));
+typedef float sem_f4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma4;
+template <> struct Mfma4<double> {
+  typedef sem_d4 V;
+  static __device__ __forceinline__ V fma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <> struct Mfma4<float> {
+  typedef sem_f4 V;
+  static __device__ __forceinline__ V fma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <typename T>
 
 __global__ void __launch_bounds__(256)
-ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* __restrict__ w,
-                 const double* __restrict__ G, const int32_t* __restrict__ rec, const double* __restrict__ Dg,
+ax_mfma15_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w,
+                 const T* __restrict__ G, const int32_t* __restrict__ rec, const T* __restrict__ Dg,
                  const uint8_t* __restrict__ dir, const int32_t* __restrict__ order, int64_t E,
-                 double* __restrict__ dpart, OpCoef<double> oc) {
+                 double* __restrict__ dpart, OpCoef<T> oc) {
+  typedef typename Mfma4<T>::V V;
   constexpr int N = 15, n1 = 16, P = 256, NN = 4096;
-  __shared__ double sU[NN];        // u, later the xi/eta part of the result
-  __shared__ double sT[NN];        // zeta derivative of u, later C
-  __shared__ double sS[4][2][P];   // per-wave A_k, B_k
+  __shared__ T sU[NN];        // u, later the xi/eta part of the result
+  __shared__ T sT[NN];        // zeta derivative of u, later C
+  __shared__ __attribute__((aligned(16))) T sS[4][2][P];  // per-wave A_k, B_k; at the end the reduction
   const int tid = threadIdx.x, wave = tid >> 6, l = tid & 63;
   const int lr = l & 15, lq = l >> 4;
+  // row of the 16x16 result held in accumulator register r: interleaved in FP64
+  // (4r + l/16), blocked in FP32 (4(l/16) + r)
+  auto orow = [lq](int r) { return std::is_same<T, double>::value ? 4 * r + lq : 4 * lq + r; };
   const int64_t pos = xcd_position(blockIdx.x, E);
   if (pos >= E) {  // whole workgroup
     if (dpart != nullptr && tid == 0) dpart[blockIdx.x] = 0.0;
@@ -395,7 +413,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
     const int cx = node_class(i0, N), cy = node_class(j0, N);
     const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
     const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
-    double uv[n1];
+    T uv[n1];
 #pragma unroll
     for (int k = 0; k < n1; ++k) {
       const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
@@ -406,7 +424,7 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
     for (int k = 0; k < n1; ++k) sU[k * P + tid] = uv[k];
   }
-  double DA[4], DB[4];  // DA[s] = D[lr][4s+lq] (A layout of D), DB[s] = D[4s+lq][lr] (B layout)
+  T DA[4], DB[4];  // DA[s] = D[lr][4s+lq] (A layout of D), DB[s] = D[4s+lq][lr] (B layout)
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     DA[s] = Dg[lr * n1 + 4 * s + lq];
@@ -417,45 +435,45 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int t = wave * 4 + q;
-    sem_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    V acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(DA[s], sU[(4 * s + lq) * P + t * 16 + lr], acc, 0, 0, 0);
+    for (int s = 0; s < 4; ++s) acc = Mfma4<T>::fma(DA[s], sU[(4 * s + lq) * P + t * 16 + lr], acc);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sT[(4 * r + lq) * P + t * 16 + lr] = acc[r];
+    for (int r = 0; r < 4; ++r) sT[orow(r) * P + t * 16 + lr] = acc[r];
   }
   __syncthreads();
   // 2. planes
-  const double* Ge = G + e * 6 * NN;
-  sem_d4 W[4];
+  const T* Ge = G + e * 6 * NN;
+  V W[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int k = wave * 4 + q;
-    const double* Uk = sU + k * P;
-    sem_d4 ur = {0.0, 0.0, 0.0, 0.0}, us = {0.0, 0.0, 0.0, 0.0};
+    const T* Uk = sU + k * P;
+    V ur = {0, 0, 0, 0}, us = {0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(Uk[lr * n1 + 4 * s + lq], DA[s], ur, 0, 0, 0);  // U_k D^T
-      us = __builtin_amdgcn_mfma_f64_16x16x4f64(DA[s], Uk[(4 * s + lq) * n1 + lr], us, 0, 0, 0);  // D U_k
+      ur = Mfma4<T>::fma(Uk[lr * n1 + 4 * s + lq], DA[s], ur);  // U_k D^T
+      us = Mfma4<T>::fma(DA[s], Uk[(4 * s + lq) * n1 + lr], us);  // D U_k
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int node = k * P + (4 * r + lq) * n1 + lr;
-      const double ut = sT[node];
-      const double g0 = Ge[0 * NN + node], g1 = Ge[1 * NN + node], g2 = Ge[2 * NN + node];
-      const double g3 = Ge[3 * NN + node], g4 = Ge[4 * NN + node], g5 = Ge[5 * NN + node];
-      const double A = g0 * ur[r] + g1 * us[r] + g2 * ut;
-      const double B = g1 * ur[r] + g3 * us[r] + g4 * ut;
-      const double C = g2 * ur[r] + g4 * us[r] + g5 * ut;
-      sS[wave][0][(4 * r + lq) * n1 + lr] = A;
-      sS[wave][1][(4 * r + lq) * n1 + lr] = B;
+      const int node = k * P + orow(r) * n1 + lr;
+      const T ut = sT[node];
+      const T g0 = Ge[0 * NN + node], g1 = Ge[1 * NN + node], g2 = Ge[2 * NN + node];
+      const T g3 = Ge[3 * NN + node], g4 = Ge[4 * NN + node], g5 = Ge[5 * NN + node];
+      const T A = g0 * ur[r] + g1 * us[r] + g2 * ut;
+      const T B = g1 * ur[r] + g3 * us[r] + g4 * ut;
+      const T C = g2 * ur[r] + g4 * us[r] + g5 * ut;
+      sS[wave][0][orow(r) * n1 + lr] = A;
+      sS[wave][1][orow(r) * n1 + lr] = B;
       sT[node] = C;  // plane k of the zeta derivative is no longer needed
     }
     __syncthreads();
-    sem_d4 wk = {0.0, 0.0, 0.0, 0.0};
+    V wk = {0, 0, 0, 0};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-      wk = __builtin_amdgcn_mfma_f64_16x16x4f64(sS[wave][0][lr * n1 + 4 * s + lq], DB[s], wk, 0, 0, 0);  // A_k D
-      wk = __builtin_amdgcn_mfma_f64_16x16x4f64(DB[s], sS[wave][1][(4 * s + lq) * n1 + lr], wk, 0, 0, 0);  // D^T B_k
+      wk = Mfma4<T>::fma(sS[wave][0][lr * n1 + 4 * s + lq], DB[s], wk);  // A_k D
+      wk = Mfma4<T>::fma(DB[s], sS[wave][1][(4 * s + lq) * n1 + lr], wk);  // D^T B_k
     }
     W[q] = wk;
     __syncthreads();
@@ -464,37 +482,37 @@ ax_mfma15_kernel(const double* __restrict__ u, double* __restrict__ y, double* _
 #pragma unroll
   for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) sU[(wave * 4 + q) * P + (4 * r + lq) * n1 + lr] = W[q][r];
+    for (int r = 0; r < 4; ++r) sU[(wave * 4 + q) * P + orow(r) * n1 + lr] = W[q][r];
   __syncthreads();
   // 3. zeta transpose and output: tile t = row j of every plane
   const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
-  const ElemCoef<double> ec = elem_coef(oc, e);
+  const ElemCoef<T> ec = elem_coef(oc, e);
   double dacc = 0.0;  // share of u . y over interior nodes, with dpart
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int t = wave * 4 + q;
-    sem_d4 acc = {0.0, 0.0, 0.0, 0.0};
+    V acc = {0, 0, 0, 0};
 #pragma unroll
-    for (int s = 0; s < 4; ++s) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(DB[s], sT[(4 * s + lq) * P + t * 16 + lr], acc, 0, 0, 0);
+    for (int s = 0; s < 4; ++s) acc = Mfma4<T>::fma(DB[s], sT[(4 * s + lq) * P + t * 16 + lr], acc);
     const int j = t, i = lr, cx = node_class(i, N), cy = node_class(j, N);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int k = 4 * r + lq;
+      const int k = orow(r);
       const NodeAddr a = node_addr(rec, e, cx, cy, k, i, j, N);
-      const double ug = (dpart != nullptr || oc.scaled || oc.ke != nullptr) ? u[a.g] : 0.0;
-      const double v = elem_value(oc, ec, e, NN, k * P + j * n1 + i, acc[r] + sU[k * P + j * n1 + i], ug);
+      const T ug = (dpart != nullptr || oc.scaled || oc.ke != nullptr) ? u[a.g] : T(0);
+      const T v = elem_value(oc, ec, e, NN, k * P + j * n1 + i, acc[r] + sU[k * P + j * n1 + i], ug);
       if (a.flags & kFlagInterior) {
-        const double yv = (masked_interior && dir[a.g]) ? 0.0 : op_value(oc, v, a.g, ug);
+        const T yv = (masked_interior && dir[a.g]) ? T(0) : op_value(oc, v, a.g, ug);
         y[a.g] = yv;
-        if (dpart != nullptr) dacc += ug * yv;
+        if (dpart != nullptr) dacc += (double)ug * (double)yv;
       } else {
         w[a.w] = v;
       }
     }
   }
   if (dpart != nullptr) {
-    __syncthreads();  // sS is reused for the reduction
-    const double tsum = group_sum<256>(dacc, &sS[0][0][0]);
+    __syncthreads();  // sS is reused for the reduction (FP64: 2 x 80 KB fills the CU's LDS exactly)
+    const double tsum = group_sum<256>(dacc, reinterpret_cast<double*>(&sS[0][0][0]));
     if (tid == 0) dpart[blockIdx.x] = tsum;
   }
 }

@@ -238,8 +238,9 @@ def test_geometry_on_the_fly_operator(N):
 
 @pytest.mark.parametrize("tile", [1, 16])
 def test_order15_operator_variants(tile):
-    """N = 15: the vector kernel and the FP64 matrix-core kernel both match the
-    oracle (two elements, one face shared, ragged permuted numbering)."""
+    """N = 15: the vector kernel and the matrix-core kernel both match the
+    oracle in FP64 and FP32 (two elements, one face shared, ragged permuted
+    numbering)."""
     from paper_1506_05996_amd import sem
     dev = _dev()
     m = meshgen.cube_mesh((2, 1, 2), perturb=0.1, seed=71)
@@ -250,6 +251,9 @@ def test_order15_operator_variants(tile):
     P = Problem(m.vtx, m.hex, 15, fine=False, coarse=False)
     u = np.random.default_rng(74).uniform(-1, 1, M.n_global)
     y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
-    assert rel_l2(y, P.A(u)) <= 1e-12
-    with pytest.raises(sem.SemError):
-        M.set_tile(16, sem.SEM_F32)
+    ref = P.A(u)
+    assert rel_l2(y, ref) <= 1e-12
+    M.set_tile(tile, sem.SEM_F32)
+    assert M.tile(sem.SEM_F32) == tile
+    y32 = M.apply_A(torch.tensor(u, device=dev, dtype=torch.float32)).double().cpu().numpy()
+    assert rel_l2(y32, ref) <= 5e-6
