@@ -26,10 +26,16 @@ Library primitives used: scipy.sparse products, scipy.linalg.cho_factor /
 cho_solve for the coarsest level.
 
 Pinned by: the aggregates partition the unknowns with sizes 1..4; the
-Galerkin matrices equal the dense products P^T A P; the cycle is exact on the
-two-level hierarchy's coarsest space (a one-level hierarchy returns A^{-1} b);
-the K-cycle as a preconditioner for CG on the coarse matrix converges in a
-number of iterations that stays flat as the mesh is refined.
+Galerkin matrices equal the dense products P^T A P; a one-level hierarchy
+returns A^{-1} b; on the last two levels the cycle equals the two-grid
+operator (I - S (I - P A_c^{-1} P^T A) S) A^{-1} with S = I - omega D^{-1} A
+(dense algebra); the two flexible-CG steps return the Galerkin projection
+V (V^T A V)^{-1} V^T b onto the two directions V = [v, v2] the cycle produced,
+with the second direction taken at the residual left by the first; planted
+mistakes (post-smoothing dropped, undamped sweep, no A-orthogonalisation, a
+wrong first step length) fail those pins; the K-cycle as a preconditioner for
+CG on the coarse matrix converges in a number of iterations that stays flat
+as the mesh is refined.
 """
 from __future__ import annotations
 

@@ -13,7 +13,12 @@ functions Phi_0 = (1-t)/2, Phi_1 = (1+t)/2).  At every GLL node:
   geometric factors (six G plus the weighted mass) fits that reading.
 
 Pinned by: sum of the lumped mass = domain volume, closed-form G on affine
-elements, and (through the operator pins) polynomial exactness.
+elements, and (through the operator pins) polynomial exactness.  The box
+sizes of the patch solves are pinned on an axis-aligned box with a different
+h along each axis, with and without random element rotations: each size equals
+the extent along the physical axis its reference axis points to, and the box
+operator built from them equals the assembled operator on an interior patch
+(sizes taken from the wrong edges fail both).
 """
 from __future__ import annotations
 

@@ -232,3 +232,77 @@ def test_h_independence_trend():
     assert two8 <= 1.25 * two4
     assert fine8 >= 1.3 * fine4
     assert two8 < fine8
+
+
+# --- box sizes h_x, h_y, h_z on anisotropic and rotated meshes (Section 4.2) ---
+ANISO = (1.0, 2.0, 3.0)  # domain lengths: h differs along each axis
+
+
+def _box_sizes_eta_for_xi(vtx, hexes):
+    """Planted mistake: h_x taken from the eta-edges."""
+    h = box_sizes(vtx, hexes).copy()
+    h[:, 0] = h[:, 1]
+    return h
+
+
+def _box_sizes_diagonal(vtx, hexes):
+    """Planted mistake: mean face-diagonal length instead of the edge length."""
+    X = vtx[np.asarray(hexes)].reshape(-1, 2, 2, 2, 3)
+    hx = np.linalg.norm(X[:, :, 1, 1] - X[:, :, 0, 0], axis=-1).mean(axis=1)
+    h = box_sizes(vtx, hexes).copy()
+    h[:, 0] = hx
+    return h
+
+
+def box_size_pin_error(fn, k=3, rotate=False):
+    """Largest deviation of fn's sizes from the extent of each element along the
+    physical axis its reference axis points to (axis-aligned box, exact)."""
+    mesh = meshgen.cube_mesh(k, lengths=ANISO)
+    if rotate:
+        mesh, _ = meshgen.rotate_elements(mesh, seed=31)
+    h = fn(mesh.vtx, mesh.hex)
+    X = mesh.vtx[mesh.hex]  # [E, 8, 3], corner a + 2b + 4c
+    err = 0.0
+    for d, corner in enumerate((1, 2, 4)):  # reference axes xi, eta, zeta
+        edge = X[:, corner] - X[:, 0]
+        axis = np.abs(edge).argmax(axis=1)
+        ref = np.array(ANISO)[axis] / k
+        err = max(err, float(np.abs(h[:, d] - ref).max()))
+    return err
+
+
+@pytest.mark.parametrize("rotate", [False, True])
+def test_box_sizes_follow_each_reference_axis(rotate):
+    assert box_size_pin_error(box_sizes, rotate=rotate) <= 1e-14
+
+
+@pytest.mark.parametrize("fn", [_box_sizes_eta_for_xi, _box_sizes_diagonal])
+def test_box_size_pin_rejects_planted_mistakes(fn):
+    assert box_size_pin_error(fn, rotate=True) > 1e-2
+
+
+def patch_identity_error(fn, rotate=False):
+    """Deviation of the box operator built with fn's sizes from the assembled
+    operator restricted to the centre element's (n+3)^3 patch, on an
+    axis-aligned box with different h along each axis."""
+    n = 3
+    mesh = meshgen.cube_mesh(3, lengths=ANISO)
+    if rotate:
+        mesh, _ = meshgen.rotate_elements(mesh, seed=33)
+    P = Problem(mesh.vtx, mesh.hex, n, coarse=False)
+    A = assemble_dense(mesh.vtx, mesh.hex, P.num.l2g, P.num.n_global, P.gll)
+    e = 13  # centre element of the 3^3 lattice
+    Ip = P.fine.Ip[e].reshape(-1)
+    assert (Ip >= 0).all()
+    As = A[np.ix_(Ip, Ip)]
+    Abox = box_operator(n, fn(mesh.vtx, mesh.hex)[e])
+    return float(np.abs(As - Abox).max() / np.abs(As).max())
+
+
+@pytest.mark.parametrize("rotate", [False, True])
+def test_fdm_equals_true_patch_operator_on_anisotropic_mesh(rotate):
+    assert patch_identity_error(box_sizes, rotate) <= 1e-12
+
+
+def test_patch_identity_rejects_swapped_axes():
+    assert patch_identity_error(_box_sizes_eta_for_xi) > 1e-2
