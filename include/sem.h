@@ -2,13 +2,17 @@
  * sem.h -- C ABI of the MI355X spectral-element Poisson solver.
  *
  * Method: Remacle, Gandham, Warburton, "GPU accelerated spectral finite
- * elements on all-hex meshes".  The library solves the Poisson special case
- * (kappa = 1, c = 0) of the model problem of Section 2 with homogeneous
- * Dirichlet data, discretised with order-N Gauss-Lobatto-Legendre (GLL)
- * spectral elements on unstructured hexahedra, by preconditioned conjugate
- * gradients (Algorithm 1) with the two-scale additive Schwarz preconditioner
- * of Section 4 (overlapping fast-diagonalisation patch solves plus an order-1
- * coarse correction).
+ * elements on all-hex meshes".  The library solves the model problem of
+ * Section 2, c u - div(kappa grad u) = s (eq. (pde)), with homogeneous
+ * Dirichlet data on a chosen node set and optional Neumann data, discretised
+ * with order-N Gauss-Lobatto-Legendre (GLL) spectral elements on unstructured
+ * hexahedra, by preconditioned conjugate gradients (Algorithm 1) with the
+ * two-scale additive Schwarz preconditioner of Section 4 (overlapping
+ * fast-diagonalisation patch solves plus an order-1 coarse correction).
+ * kappa and c are constants by default (kappa = 1, c = 0: the Poisson
+ * problem), or one value per element, or one value per local node.  Also: an
+ * FP32-refined solve, batched solves of many meshes, backward Euler steps of
+ * the heat equation of Section 6.2 and an aggregation-AMG coarse solver.
  *
  * Conventions shared by every entry point
  *   - Mesh input is host memory and is copied; the handle owns every buffer it
@@ -148,7 +152,15 @@ int sem_mesh_boundary_mask(sem_mesh m, uint8_t* mask_host); /* [n_global], 1 = D
 int sem_mesh_geometry(sem_mesh m, double* G_host, double* mass_host);
 
 /* Replace the Dirichlet set (host in, [n_global], 1 = Dirichlet).  Re-derives the
-   coarse vertex set and refactors the coarse matrix. */
+   coarse vertex set and refactors the coarse matrix.
+   The Dirichlet set is state of the handle, not an argument of each hot-path
+   call: the coarse space of Section 4.1 depends on it (its free vertices, the
+   nested dissection of their graph and the factor of the coarse matrix), so a
+   new set costs a new dissection and factorisation of the coarse matrix on the
+   host and device, synchronously (the set-up's coarse part: tens of
+   milliseconds on small meshes, seconds at tens of millions of nodes), while a
+   fixed set costs nothing per call (the element kernels read it only for
+   elements that touch it).  Calls enqueued before this one complete first. */
 int sem_mesh_set_dirichlet(sem_mesh m, const uint8_t* mask_host);
 
 /*
@@ -178,7 +190,13 @@ int sem_coarse_solve(sem_mesh m, const double* R_dev, double* Z_dev, void* strea
  * iterative refinement (true residual b - A x in FP64) around inner PCG solves
  * whose operator, gather and patch solves run in FP32, with FP64 dot products,
  * scalars and coarse solve.  Returns SEM_OK, SEM_ENOCONV (stats filled),
- * SEM_EBREAKDOWN, or an error.  b = 0 gives x = 0 and 0 iterations.
+ * SEM_EBREAKDOWN, or an error.  Only the values of b on free nodes take part
+ * (b is read as 0 on the Dirichlet set); ||b|| in the stopping rule is the norm
+ * of those values.  b = 0 gives x = 0 and 0 iterations; with use_x0, a start
+ * whose residual already meets the tolerance returns after 0 iterations.
+ * After SEM_EBREAKDOWN x holds the last iterate with finite scalars.
+ * Work vectors (5 of n_global FP64, and 5 FP32 for the refined form) are
+ * allocated by the first solve that needs them and kept by the handle.
  */
 int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solve_opts* o,
                   sem_solve_stats* st, void* stream);
@@ -304,9 +322,13 @@ int sem_batch_setup(int n, const double* const* vtx, const int64_t* n_vtx, const
 int sem_batch_sizes(sem_batch b, int64_t* n_global);
 
 /* Solve A_i x_i = b_i for all instances.  b_dev, x_dev: host arrays of n device
-   pointers (FP64, [n_global[i]] each, in each instance's own numbering).
-   st: optional array of n statistics.  Returns SEM_OK when every instance
-   converged, SEM_ENOCONV or SEM_EBREAKDOWN otherwise (statistics filled). */
+   pointers (FP64, [n_global[i]] each, in each instance's own numbering; b is
+   read as 0 on each instance's Dirichlet set).  As in sem_pcg_solve, the FP64
+   form confirms each instance with its true residual b - A x and continues
+   from it the instances still above their tolerance (outer_iterations counts
+   these restarts).  st: optional array of n statistics.  Returns SEM_OK when
+   every instance converged, SEM_ENOCONV or SEM_EBREAKDOWN otherwise
+   (statistics filled). */
 int sem_batch_solve(sem_batch b, const double* const* b_dev, double* const* x_dev, const sem_solve_opts* o,
                     sem_solve_stats* st, void* stream);
 
@@ -326,7 +348,7 @@ int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int 
    (N+1)^2 lanes each, at most 1024 lanes), 16 for the matrix-core kernel
    (N = 15 only, FP64 or FP32), or 32 for the kernel that rebuilds the geometric
    factors at every node from the element's 8 vertices instead of reading them
-   (Section 3; same factors up to rounding).  Chosen by the autotuner or the
+   (the r' kernel of Section 5.1 and Table 3; same factors up to rounding).  Chosen by the autotuner or the
    default for the order; sem_mesh_set_tile overrides it (SEM_EINVAL if not
    available). */
 int sem_mesh_tile(sem_mesh m, int dtype, int* epb);

@@ -28,7 +28,7 @@ namespace sem {
 
 // per-instance scalar slots
 enum : int {
-  kRz = 0, kPw, kAlpha, kBeta, kRr, kBb, kActive, kIters, kTol2, kFlag, kNorm, kScal  // kScal = stride
+  kRz = 0, kPw, kAlpha, kBeta, kRr, kBb, kActive, kIters, kTol2, kFlag, kNorm, kRestarts, kScal  // kScal = stride
 };
 constexpr int64_t kChunk = 16384;  // nodes per reduction chunk
 
@@ -205,6 +205,39 @@ seg_residual_kernel(double* __restrict__ r, const double* __restrict__ b, const 
   if (threadIdx.x == 0) part[cid] = s;
 }
 
+// After a batched FP64 solve, part holds each instance's true ||b - A x||^2 (by
+// chunks): instances whose true residual is still above the tolerance become
+// active again (PCG restarts from it), the others stay stopped; counts restarts.
+__global__ void __launch_bounds__(64)
+seg_restart_kernel(const double* __restrict__ part, const int32_t* __restrict__ inst_chunk_off,
+                   double* __restrict__ sc, int n, double* __restrict__ nactive) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int32_t c = inst_chunk_off[i]; c < inst_chunk_off[i + 1]; ++c) s += part[c];
+    double* S = sc + (int64_t)i * kScal;
+    S[kRr] = s;
+    if (!isfinite(s)) S[kFlag] = 1.0;
+    const bool act = S[kFlag] == 0.0 && S[kBb] > 0.0 && s > S[kTol2];
+    S[kActive] = act ? 1.0 : 0.0;
+    if (act) {
+      S[kRestarts] += 1.0;
+      atomicAdd(&cnt, 1);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) nactive[0] = (double)cnt;
+}
+
+// b = 0 on the Dirichlet set (its values there do not take part in the solve)
+__global__ void __launch_bounds__(256)
+mask_vec_kernel(double* __restrict__ v, const uint8_t* __restrict__ dir, int64_t n) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
+    if (dir[q]) v[q] = 0.0;
+}
+
 // per-instance scalar initialisation of a PCG run: rz, active, tol2, counters
 __global__ void seg_init_kernel(double* __restrict__ sc, const double* __restrict__ bb_src, int bb_slot, int n,
                                 double rtol2) {
@@ -215,6 +248,7 @@ __global__ void seg_init_kernel(double* __restrict__ sc, const double* __restric
     S[kTol2] = rtol2 * bb;
     S[kRr] = bb;
     S[kIters] = 0.0;
+    S[kRestarts] = 0.0;
     S[kFlag] = 0.0;
     S[kActive] = (bb > 0.0 && isfinite(bb) && bb > S[kTol2]) ? 1.0 : 0.0;
   }
@@ -373,19 +407,24 @@ double read_active(sem_batch b, hipStream_t s) {
   return v;
 }
 
-// PCG on all instances: x, r given (r = rhs), returns iterations performed
+// PCG on all instances: x, r given (r = rhs), returns the batched iterations
+// performed.  restart: the scalars (tolerances, active flags, counters) come
+// from seg_restart_kernel instead of a fresh start from ||r||.
 template <typename T>
-int batched_pcg(sem_batch b, double rtol, int max_iter, int pc, int check_every, hipStream_t s) {
-  // per-instance ||r||^2 -> scalars, tolerance, active flags
-  for (auto& g : b->groups) {
-    auto& V = [&]() -> Vecs<T>& {
-      if constexpr (std::is_same<T, double>::value) return g.f64; else return g.f32;
-    }();
-    seg_dot<T, T>(b, g, V.v[1].p, V.v[1].p, s);
+int batched_pcg(sem_batch b, double rtol, int max_iter, int pc, int check_every, hipStream_t s,
+                bool restart = false) {
+  if (!restart) {
+    // per-instance ||r||^2 -> scalars, tolerance, active flags
+    for (auto& g : b->groups) {
+      auto& V = [&]() -> Vecs<T>& {
+        if constexpr (std::is_same<T, double>::value) return g.f64; else return g.f32;
+      }();
+      seg_dot<T, T>(b, g, V.v[1].p, V.v[1].p, s);
+    }
+    seg_final(b, b->sc.p, kRr, 0, s);
+    hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(64), 0, s, b->sc.p, (const double*)b->sc.p, (int)kRr, b->n,
+                       rtol * rtol);
   }
-  seg_final(b, b->sc.p, kRr, 0, s);
-  hipLaunchKernelGGL(seg_init_kernel, dim3(1), dim3(64), 0, s, b->sc.p, (const double*)b->sc.p, (int)kRr, b->n,
-                     rtol * rtol);
   for (auto& g : b->groups) {
     auto& V = [&]() -> Vecs<T>& {
       if constexpr (std::is_same<T, double>::value) return g.f64; else return g.f32;
@@ -591,21 +630,44 @@ int sem_batch_solve(sem_batch b, const double* const* b_dev, double* const* x_de
     const bool refined = o->mode == SEM_SOLVE_FP32_REFINED;
     if (refined && !b->groups.front().f32.v[0].p) throw Error{SEM_EUNSUPPORTED, "batch built without FP32 copies"};
     if (o->use_x0) throw Error{SEM_EUNSUPPORTED, "batched solves start from x = 0"};
-    // b -> union slot 5; x = 0
+    // b -> union slot 5 (zero on the Dirichlet set); x = 0
     copy_in(b, b_dev, 5, s);
-    for (auto& g : b->groups)
+    for (auto& g : b->groups) {
+      hipLaunchKernelGGL(mask_vec_kernel, dim3(grid_for(g.mesh->T.n_global)), dim3(256), 0, s, g.f64.v[5].p,
+                         (const uint8_t*)g.mesh->dir.p, g.mesh->T.n_global);
       hipLaunchKernelGGL((fill_vec_kernel<double>), dim3(grid_for(g.mesh->T.n_global)), dim3(256), 0, s,
                          g.f64.v[0].p, 0.0, g.mesh->T.n_global);
+    }
     std::vector<int> iters(b->n, 0), outer(b->n, 0);
     std::vector<double> host_sc((size_t)b->n * kScal), host_out((size_t)b->n * kScal);
     if (!refined) {
       for (auto& g : b->groups)
         hipLaunchKernelGGL((copy_vec_kernel<double>), dim3(grid_for(g.mesh->T.n_global)), dim3(256), 0, s,
                            g.f64.v[1].p, (const double*)g.f64.v[5].p, g.mesh->T.n_global);
-      batched_pcg<double>(b, o->rtol, o->max_iter, o->pc, check, s);
+      int total = batched_pcg<double>(b, o->rtol, o->max_iter, o->pc, check, s);
+      // the recursive residual can drift below the true one: b - A x per
+      // instance, and PCG again from it for the instances still above their
+      // tolerance (as the single solve does)
+      for (;;) {
+        for (auto& g : b->groups) {
+          apply_A<double>(g.mesh.get(), g.f64.v[0].p, g.f64.v[4].p, s);
+          if (!g.chunk_ids.empty())
+            hipLaunchKernelGGL(seg_residual_kernel, dim3((unsigned)g.chunk_ids.size()), dim3(256), 0, s, g.f64.v[1].p,
+                               (const double*)g.f64.v[5].p, (const double*)g.f64.v[4].p, g.d_chunk_ids.p,
+                               b->d_chunks.p, b->part.p);
+        }
+        hipLaunchKernelGGL(seg_restart_kernel, dim3(1), dim3(64), 0, s, (const double*)b->part.p,
+                           (const int32_t*)b->d_inst_chunk_off.p, b->sc.p, b->n, b->nactive.p);
+        SEM_HIP(hipGetLastError());
+        if (read_active(b, s) == 0.0 || total >= o->max_iter) break;
+        total += batched_pcg<double>(b, o->rtol, o->max_iter - total, o->pc, check, s, true);
+      }
       SEM_HIP(hipMemcpyAsync(host_sc.data(), b->sc.p, host_sc.size() * sizeof(double), hipMemcpyDeviceToHost, s));
       SEM_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i < b->n; ++i) iters[i] = (int)host_sc[(size_t)i * kScal + kIters];
+      for (int i = 0; i < b->n; ++i) {
+        iters[i] = (int)host_sc[(size_t)i * kScal + kIters];
+        outer[i] = (int)host_sc[(size_t)i * kScal + kRestarts];
+      }
     } else {
       // outer: r = b - A x in FP64 per instance; inner: FP32 batched PCG on r / ||r||
       for (int it = 0; it <= o->max_outer; ++it) {

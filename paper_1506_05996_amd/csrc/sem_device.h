@@ -122,10 +122,21 @@ struct sem_mesh_s {
   DBuf<double> amg_inv, amg_sc;
   DBuf<int32_t> amg_nd, amg_pos;
   hipGraphExec_t amg_graph = nullptr;
-  // PCG work
+  // PCG work: the handle's own buffers (allocated by the first solve that
+  // needs them) ...
   DBuf<double> v64[5];
   DBuf<float> v32[5];
   DBuf<double> part, sc, dpart;
+  // ... and the pointers one solve works in: the buffers above, or views into
+  // the library's static scratch array (sem_pcg_solve_noalloc)
+  struct SolveWork {
+    double* v64[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    float* v32[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double* part = nullptr;   // kRedBlocks partial sums
+    double* sc = nullptr;     // 16 device scalars of Algorithm 1
+    double* dpart = nullptr;  // per-workgroup partial dot products of the operator and preconditioner
+  } wk;
+  bool no_alloc = false;      // inside sem_pcg_solve_noalloc: no lazy set-up may run
 };
 
 namespace sem {

@@ -263,14 +263,14 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
 // product taken from the operator's own kernels (no extra pass over u and y)
 template <typename T>
 void apply_A_dot(sem_mesh m, const T* u, T* y, int dst, int mode, hipStream_t s) {
-  const int64_t na = apply_A_elements<T>(m, u, y, s, m->dpart.p);
-  const int64_t ng = launch_gs<T>(m, y, s, u, m->dpart.p + na, u);
+  const int64_t na = apply_A_elements<T>(m, u, y, s, m->wk.dpart);
+  const int64_t ng = launch_gs<T>(m, y, s, u, m->wk.dpart + na, u);
   const int64_t n = na + ng;
   const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
   const int nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->dpart.p, m->part.p, n,
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
                      chunk);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dst, mode);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dst, mode);
   SEM_HIP(hipGetLastError());
 }
 
@@ -478,64 +478,61 @@ void amg_sweeps(sem_mesh m, hipStream_t s) {
   SEM_HIP(hipGetLastError());
 }
 
-void amg_solve(sem_mesh m, hipStream_t s) {
-  if (m->amg.empty()) throw Error{SEM_EINVAL, "AMG hierarchy not built"};
-  if (m->direct_coarse) {
-    amg_sweeps(m, s);
-    return;
-  }
-  if (!m->amg_graph) {
-    if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    SEM_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
-    try {
+// Capture the coarse solve of the current coarse solver (nested-dissection
+// sweeps or one K-cycle) once, on a private stream; the preconditioner replays
+// it on the caller's stream.  Built at set-up and whenever the coarse matrix or
+// solver changes.
+void build_coarse_graph(sem_mesh m) {
+  if (m->T.nc == 0) return;
+  const bool amg = m->coarse_solver == SEM_COARSE_AMG;
+  if (amg && m->amg.empty()) throw Error{SEM_EINVAL, "AMG hierarchy not built"};
+  hipGraphExec_t& exec = amg ? m->amg_graph : m->coarse_graph;
+  if (exec) return;
+  if (m->no_alloc) throw Error{SEM_EINVAL, "coarse-solve graph missing (it is built at set-up)"};
+  if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
+  hipGraph_t g = nullptr;
+  SEM_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    if (amg)
       amg_sweeps(m, m->capture_stream);
-    } catch (...) {
-      (void)hipStreamEndCapture(m->capture_stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    SEM_HIP(hipStreamEndCapture(m->capture_stream, &g));
-    hipError_t err = hipGraphInstantiate(&m->amg_graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (err != hipSuccess) {
-      m->amg_graph = nullptr;
-      throw Error{SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
-    }
+    else
+      coarse_sweeps(m, m->capture_stream);
+  } catch (...) {
+    (void)hipStreamEndCapture(m->capture_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    throw;
   }
-  SEM_HIP(hipGraphLaunch(m->amg_graph, s));
+  SEM_HIP(hipStreamEndCapture(m->capture_stream, &g));
+  hipError_t err = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (err != hipSuccess) {
+    exec = nullptr;
+    throw Error{SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
+  }
 }
 
-// capture the sweeps once (on a private stream) and replay them on the caller's stream
+// Rlev (coarse order) -> Zv (vertex order): the coarse solve P_0
 void coarse_solve_tree(sem_mesh m, hipStream_t s) {
-  if (m->coarse_solver == SEM_COARSE_AMG) {
-    amg_solve(m, s);
+  const bool amg = m->coarse_solver == SEM_COARSE_AMG;
+  if (m->direct_coarse) {  // inside an enclosing capture: launch the kernels themselves
+    if (amg)
+      amg_sweeps(m, s);
+    else
+      coarse_sweeps(m, s);
     return;
   }
-  if (m->direct_coarse) {
-    coarse_sweeps(m, s);
-    return;
-  }
-  if (!m->coarse_graph) {
-    if (!m->capture_stream) SEM_HIP(hipStreamCreateWithFlags(&m->capture_stream, hipStreamNonBlocking));
-    hipGraph_t g = nullptr;
-    SEM_HIP(hipStreamBeginCapture(m->capture_stream, hipStreamCaptureModeThreadLocal));
-    try {
-      coarse_sweeps(m, m->capture_stream);
-    } catch (...) {
-      (void)hipStreamEndCapture(m->capture_stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    SEM_HIP(hipStreamEndCapture(m->capture_stream, &g));
-    hipError_t err = hipGraphInstantiate(&m->coarse_graph, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (err != hipSuccess) {
-      m->coarse_graph = nullptr;
-      throw Error{SEM_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(err)};
-    }
-  }
-  SEM_HIP(hipGraphLaunch(m->coarse_graph, s));
+  build_coarse_graph(m);
+  SEM_HIP(hipGraphLaunch(amg ? m->amg_graph : m->coarse_graph, s));
+}
+
+// the second stream (and its fork/join events) that runs the coarse chain
+// beside the patch solves; created at set-up
+void ensure_side_stream(sem_mesh m) {
+  if (m->side_stream) return;
+  if (m->no_alloc) throw Error{SEM_EINVAL, "side stream missing (it is created at set-up)"};
+  SEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
+  SEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
+  SEM_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
 }
 
 template <typename T>
@@ -568,11 +565,7 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
   // coarse chain do not hold them back.
   hipStream_t sc = s;
   if (coarse && fine) {
-    if (!m->side_stream) {
-      SEM_HIP(hipStreamCreateWithFlags(&m->side_stream, hipStreamNonBlocking));
-      SEM_HIP(hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming));
-      SEM_HIP(hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming));
-    }
+    ensure_side_stream(m);
     SEM_HIP(hipEventRecord(m->ev_fork, s));
     SEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
     sc = m->side_stream;
@@ -593,12 +586,12 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
     schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s);
     return;
   }
-  const int64_t n = schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s, r, m->dpart.p);
+  const int64_t n = schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s, r, m->wk.dpart);
   const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
   const int nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->dpart.p, m->part.p, n,
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
                      chunk);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dot_dst, dot_mode);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dot_dst, dot_mode);
   SEM_HIP(hipGetLastError());
 }
 
@@ -742,6 +735,7 @@ void factor_coarse(sem_mesh m) {
     }
   }
   SEM_HIP(hipDeviceSynchronize());
+  build_coarse_graph(m);
 }
 
 void upload_all(sem_mesh m) {
@@ -811,81 +805,98 @@ void upload_all(sem_mesh m) {
   m->Zv.alloc(std::max<int64_t>(T.V, 1));
   m->part.alloc(kRedBlocks);
   m->sc.alloc(16);
+  ensure_side_stream(m);
   factor_coarse(m);
 }
 
+// partial dot products of the operator and the preconditioner's sum (one per
+// element workgroup at most, one per gather workgroup)
+size_t dpart_count(sem_mesh m) { return (size_t)(xcd_grid(m->T.E) + blocks_for(m->T.base_i)); }
+
+// the handle's own solve buffers (allocated on first need) as the work of the next solve
 void ensure_work(sem_mesh m, bool need32) {
   const int64_t n = m->T.n_global;
   for (auto& b : m->v64)
     if (b.n != (size_t)n) b.alloc(n);
-  // partial dot products of the operator (one per element workgroup at most,
-  // one per gather workgroup)
-  const size_t nd = (size_t)(xcd_grid(m->T.E) + blocks_for(m->T.base_i));
+  const size_t nd = dpart_count(m);
   if (m->dpart.n < nd) m->dpart.alloc(nd);
   if (need32)
     for (auto& b : m->v32)
       if (b.n != (size_t)n) b.alloc(n);
+  for (int q = 0; q < 5; ++q) {
+    m->wk.v64[q] = m->v64[q].p;
+    m->wk.v32[q] = need32 ? m->v32[q].p : nullptr;
+  }
+  m->wk.part = m->part.p;
+  m->wk.sc = m->sc.p;
+  m->wk.dpart = m->dpart.p;
 }
 
 template <typename TA, typename TB>
 void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s) {
   const int64_t n = m->T.n_global;
   const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
-  hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, s, a, b, m->part.p, n,
+  hipLaunchKernelGGL((dot_partial_kernel<TA, TB>), dim3(nb), dim3(kRedThreads), 0, s, a, b, m->wk.part, n,
                      (int)aligned16(a, b));
   SEM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, dst, mode);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dst, mode);
   SEM_HIP(hipGetLastError());
 }
 
 double read_scalar(sem_mesh m, int idx, hipStream_t s) {
   double v = 0.0;
-  SEM_HIP(hipMemcpyAsync(&v, m->sc.p + idx, sizeof(double), hipMemcpyDeviceToHost, s));
+  SEM_HIP(hipMemcpyAsync(&v, m->wk.sc + idx, sizeof(double), hipMemcpyDeviceToHost, s));
   SEM_HIP(hipStreamSynchronize(s));
   return v;
 }
 
-// One PCG solve (Algorithm 1) on vectors of type T; x, r in/out.  Returns
-// iterations; *rel gets ||r|| / rnorm0-scale; status via the return code.
+// One PCG solve (Algorithm 1) on vectors of type T; x, r in/out (r holds the
+// residual of x, rr0 = ||r||^2).  Returns the status; *iters gets the
+// iterations, *rel the last ||r|| / ||b||.  A start that already meets the
+// tolerance returns at once; after a breakdown x keeps the last finite iterate
+// (the vector updates skip themselves once the flag is set).
 template <typename T>
-int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, int pc, int check_every,
+int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int max_iter, int pc, int check_every,
              hipStream_t s, int* iters, double* rel, sem_solve_stats* st) {
   T* z;
   T* p;
   T* w;
   if constexpr (std::is_same<T, double>::value) {
-    z = m->v64[2].p;
-    p = m->v64[3].p;
-    w = m->v64[4].p;
+    z = m->wk.v64[2];
+    p = m->wk.v64[3];
+    w = m->wk.v64[4];
   } else {
-    z = m->v32[2].p;
-    p = m->v32[3].p;
-    w = m->v32[4].p;
+    z = m->wk.v32[2];
+    p = m->wk.v32[3];
+    w = m->wk.v32[4];
   }
+  double* sc = m->wk.sc;
   const int64_t n = m->T.n_global;
   const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
   const int gb = grid_stride_blocks(n);
-  hipLaunchKernelGGL((fill_kernel<double>), dim3(1), dim3(kGS), 0, s, m->sc.p, 0.0, (int64_t)7);
-  precond_dot<T>(m, r, z, pc, 0, 0, s);
-  hipLaunchKernelGGL((copy_kernel<T, T>), dim3(gb), dim3(kGS), 0, s, p, z, n);
   const double tol2 = rtol * rtol * bnorm2;
   int k = 0;
-  double rr = bnorm2;
+  double rr = rr0;
+  *iters = 0;
+  *rel = std::sqrt(rr / bnorm2);
+  if (rr <= tol2) return SEM_OK;
+  hipLaunchKernelGGL((fill_kernel<double>), dim3(1), dim3(kGS), 0, s, sc, 0.0, (int64_t)7);
+  precond_dot<T>(m, r, z, pc, 0, 0, s);
+  hipLaunchKernelGGL((copy_kernel<T, T>), dim3(gb), dim3(kGS), 0, s, p, z, n);
   int status = SEM_ENOCONV;
-  if (rr <= tol2) status = SEM_OK;
   bool pending_x = false;  // x += alpha p of the last iteration not yet applied
-  while (status != SEM_OK && k < max_iter) {
+  while (k < max_iter) {
     apply_A_dot<T>(m, p, w, 1, 1, s);
-    hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)m->sc.p,
-                       m->part.p, n, (int)aligned16(r, w));
+    hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)sc,
+                       m->wk.part, n, (int)aligned16(r, w));
     SEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 4, 0);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, sc, nb, 4, 0);
     ++k;
     pending_x = true;
     if (k % check_every == 0 || k == max_iter) {
       // r^T r (slot 4) and the breakdown flag (slot 6) in one read-back
       double sc46[3];
-      SEM_HIP(hipMemcpyAsync(sc46, m->sc.p + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
+      SEM_HIP(hipMemcpyAsync(sc46, sc + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
       SEM_HIP(hipStreamSynchronize(s));
       rr = sc46[0];
       const double flag = sc46[2];
@@ -901,13 +912,13 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rtol, int max_iter, i
       }
     }
     precond_dot<T>(m, r, z, pc, 5, 2, s);
-    hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)m->sc.p, n,
+    hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)sc, n,
                        (int)aligned16(x, p, z));
     SEM_HIP(hipGetLastError());
     pending_x = false;
   }
-  if (pending_x) {
-    hipLaunchKernelGGL((update_x_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, (const T*)p, (const double*)m->sc.p, n);
+  if (pending_x && status != SEM_EBREAKDOWN) {
+    hipLaunchKernelGGL((update_x_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, (const T*)p, (const double*)sc, n);
     SEM_HIP(hipGetLastError());
   }
   *iters = k;
@@ -1079,19 +1090,29 @@ void set_node_coefficients(sem_mesh m, const double* kap, const double* c) {
   factor_coarse(m);
 }
 
+// The solve behind sem_pcg_solve, in the work buffers m->wk (set by the caller).
+// b counts on the free nodes only: r = mask(b - A x), ||b|| = ||mask(b)||.
 int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, sem_solve_stats* st,
                hipStream_t s) {
   auto t0 = std::chrono::steady_clock::now();
   const int64_t n = m->T.n_global;
   const bool refined = o->mode == SEM_SOLVE_FP32_REFINED;
-  if (refined && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
-  ensure_work(m, refined);
+  if (refined && (!m->fp32 || m->wk.v32[0] == nullptr)) throw Error{SEM_EUNSUPPORTED, "no FP32 work buffers"};
   const int gb = grid_stride_blocks(n);
   const int nb = (int)std::min<int64_t>(kRedBlocks, blocks_for(n, kRedThreads));
   const int check = std::max(1, o->check_every);
   if (st) st->history_len = 0;
-  dot<double, double>(m, b, b, 7, 0, s);
-  const double bnorm2 = read_scalar(m, 7, s);
+  double* r64 = m->wk.v64[1];
+  double* Ax = m->wk.v64[4];
+  // r = mask(b - A x) with ||r||^2 into scalar slot `slot` (Ax = NULL: r = mask(b))
+  auto residual = [&](const double* ax, int slot) {
+    hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r64, b, ax, (const uint8_t*)m->dir.p,
+                       m->wk.part, n);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, slot, 0);
+    SEM_HIP(hipGetLastError());
+    return read_scalar(m, slot, s);
+  };
+  const double bnorm2 = residual(nullptr, 7);
   int status = SEM_OK, iters = 0, outer = 0;
   double rel = 0.0;
   if (!std::isfinite(bnorm2)) {
@@ -1101,26 +1122,23 @@ int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, 
     SEM_HIP(hipGetLastError());
     SEM_HIP(hipStreamSynchronize(s));
   } else if (!refined) {
-    double* r = m->v64[1].p;
+    double rr0 = bnorm2;  // x = 0: r = mask(b) already
     if (o->use_x0) {
-      apply_A<double>(m, x, m->v64[4].p, s);
-      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r, b, m->v64[4].p, m->part.p, n);
+      apply_A<double>(m, x, Ax, s);
+      rr0 = residual(Ax, 8);
     } else {
       hipLaunchKernelGGL((fill_kernel<double>), dim3(gb), dim3(kGS), 0, s, x, 0.0, n);
-      hipLaunchKernelGGL((copy_kernel<double, double>), dim3(gb), dim3(kGS), 0, s, r, b, n);
+      SEM_HIP(hipGetLastError());
     }
-    SEM_HIP(hipGetLastError());
-    status = pcg_core<double>(m, x, r, bnorm2, o->rtol, o->max_iter, o->pc, check, s, &iters, &rel, st);
+    status = !std::isfinite(rr0) ? SEM_EBREAKDOWN
+                                 : pcg_core<double>(m, x, r64, bnorm2, rr0, o->rtol, o->max_iter, o->pc, check, s,
+                                                    &iters, &rel, st);
     // the recursive residual can drift below the true one: confirm with
     // b - A x and restart from the true residual while it is above the tolerance
     const double tol2 = o->rtol * o->rtol * bnorm2;
-    double* Ax = m->v64[4].p;
     while (status == SEM_OK) {
       apply_A<double>(m, x, Ax, s);
-      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r, b, Ax, m->part.p, n);
-      hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 8, 0);
-      SEM_HIP(hipGetLastError());
-      const double rr = read_scalar(m, 8, s);
+      const double rr = residual(Ax, 8);
       rel = std::sqrt(rr / bnorm2);
       if (!std::isfinite(rr)) {
         status = SEM_EBREAKDOWN;
@@ -1133,24 +1151,19 @@ int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, 
       }
       ++outer;
       int it = 0;
-      status = pcg_core<double>(m, x, r, bnorm2, o->rtol, o->max_iter - iters, o->pc, check, s, &it, &rel, st);
+      status = pcg_core<double>(m, x, r64, bnorm2, rr, o->rtol, o->max_iter - iters, o->pc, check, s, &it, &rel, st);
       iters += it;
     }
   } else {
     // outer FP64 refinement around FP32 inner PCG solves
-    double* r64 = m->v64[1].p;
-    double* Ax = m->v64[4].p;
-    float* d32 = m->v32[0].p;
-    float* r32 = m->v32[1].p;
+    float* d32 = m->wk.v32[0];
+    float* r32 = m->wk.v32[1];
     if (!o->use_x0) hipLaunchKernelGGL((fill_kernel<double>), dim3(gb), dim3(kGS), 0, s, x, 0.0, n);
     status = SEM_ENOCONV;
     const double tol2 = o->rtol * o->rtol * bnorm2;
     for (outer = 0; outer <= o->max_outer; ++outer) {
       apply_A<double>(m, x, Ax, s);
-      hipLaunchKernelGGL(residual_kernel, dim3(nb), dim3(kRedThreads), 0, s, r64, b, Ax, m->part.p, n);
-      hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->part.p, m->sc.p, nb, 8, 0);
-      SEM_HIP(hipGetLastError());
-      const double rr = read_scalar(m, 8, s);
+      const double rr = residual(Ax, 8);
       rel = std::sqrt(rr / bnorm2);
       if (st && st->history && st->history_len < st->history_cap) st->history[st->history_len++] = rel;
       if (!std::isfinite(rr)) {
@@ -1171,8 +1184,8 @@ int solve_impl(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, 
       const double r32n2 = read_scalar(m, 9, s);
       int it = 0;
       double irel = 0.0;
-      const int st_in = pcg_core<float>(m, d32, r32, r32n2, o->inner_rtol, o->max_iter, o->pc, check, s, &it, &irel,
-                                        nullptr);
+      const int st_in = pcg_core<float>(m, d32, r32, r32n2, r32n2, o->inner_rtol, o->max_iter, o->pc, check, s, &it,
+                                        &irel, nullptr);
       iters += it;
       if (st_in == SEM_EBREAKDOWN) {
         status = SEM_EBREAKDOWN;
@@ -1618,6 +1631,8 @@ int sem_pcg_solve(sem_mesh m, const double* b, double* x, const sem_solve_opts* 
   if (o->pc < 0 || o->pc > 3 || o->max_iter < 0 || !(o->rtol >= 0.0)) return SEM_EINVAL;
   return guarded([&]() -> int {
     SEM_HIP(hipSetDevice(m->device));
+    if (o->mode == SEM_SOLVE_FP32_REFINED && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+    ensure_work(m, o->mode == SEM_SOLVE_FP32_REFINED);
     return solve_impl(m, b, x, o, st, (hipStream_t)stream);
   });
 }
@@ -1679,11 +1694,13 @@ int sem_mesh_set_coarse_solver(sem_mesh m, int solver) {
       } catch (...) {
         m->coarse_solver = SEM_COARSE_EXACT;
         m->amg.clear();
+        build_coarse_graph(m);
         throw;
       }
     } else {
       m->amg.clear();
     }
+    build_coarse_graph(m);
     return SEM_OK;
   });
 }
@@ -1731,6 +1748,8 @@ int sem_heat_step(sem_mesh m, double kappa, double dt, const double* u_prev, con
     if (u_next != u_prev) SEM_HIP(hipMemcpyAsync(u_next, u_prev, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     sem_solve_opts oo = *o;
     oo.use_x0 = 1;
+    if (oo.mode == SEM_SOLVE_FP32_REFINED && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+    ensure_work(m, oo.mode == SEM_SOLVE_FP32_REFINED);
     return solve_impl(m, m->hb.p, u_next, &oo, st, s);
   });
 }

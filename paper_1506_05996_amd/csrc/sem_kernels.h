@@ -144,8 +144,8 @@ __device__ __forceinline__ int64_t xcd_position(int64_t b, int64_t nlogical) {
 inline int64_t xcd_grid(int64_t nlogical) { return ((nlogical + 7) / 8) * 8; }
 
 // GEO = false: the factors G are read from memory (6 per node).  GEO = true:
-// they are rebuilt at every node from the element's 8 vertices (Section 3,
-// the variant that trades the factor stream for arithmetic): the columns of
+// they are rebuilt at every node from the element's 8 vertices (the r' kernel
+// of Section 5.1 and Table 3, which trades the factor stream for arithmetic): the columns of
 // the Jacobian of the trilinear map, c0 = dx/dxi etc., their cross products
 // a0 = c1 x c2, a1 = c2 x c0, a2 = c0 x c1 (the rows of det J . J^-1), and
 // G_ab = rho_i rho_j rho_k (a_a . a_b) / det J with det J = c0 . a0, the same
@@ -1357,11 +1357,13 @@ update_r_kernel(T* __restrict__ r, const T* __restrict__ w, const double* __rest
   if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-// x += alpha p (this iteration's alpha); p = z + beta p
+// x += alpha p (this iteration's alpha); p = z + beta p.  Nothing once the
+// breakdown flag is set (x keeps its last finite iterate).
 template <typename T>
 __global__ void __launch_bounds__(256)
 update_px_kernel(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ z, const double* __restrict__ sc,
                  int64_t n, int pairs) {
+  if (sc[6] != 0.0) return;  // whole grid
   typedef typename Pair2<T>::type T2;
   const T al = (T)sc[2];
   const T beta = (T)sc[3];
@@ -1394,10 +1396,11 @@ update_px_kernel(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ z, 
   }
 }
 
-// x += alpha p (the last iteration's deferred update)
+// x += alpha p (the last iteration's deferred update; nothing after a breakdown)
 template <typename T>
 __global__ void __launch_bounds__(256)
 update_x_kernel(T* __restrict__ x, const T* __restrict__ p, const double* __restrict__ sc, int64_t n) {
+  if (sc[6] != 0.0) return;  // whole grid
   const T al = (T)sc[2];
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x)
     x[q] += al * p[q];
@@ -1425,14 +1428,15 @@ __global__ void __launch_bounds__(256) fill_kernel(T* __restrict__ d, T v, int64
     d[q] = v;
 }
 
-// r = b - Ax (FP64) with partial sums of r^T r
+// r = b - Ax (FP64) on the free nodes, 0 on the Dirichlet set (Ax = NULL:
+// r = b there), with partial sums of r^T r
 __global__ void __launch_bounds__(kRedThreads)
 residual_kernel(double* __restrict__ r, const double* __restrict__ b, const double* __restrict__ Ax,
-                double* __restrict__ part, int64_t n) {
+                const uint8_t* __restrict__ dir, double* __restrict__ part, int64_t n) {
   __shared__ double sh[kRedThreads / 64];
   double s = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += (int64_t)gridDim.x * blockDim.x) {
-    const double v = b[q] - Ax[q];
+    const double v = dir[q] ? 0.0 : b[q] - (Ax != nullptr ? Ax[q] : 0.0);
     r[q] = v;
     s += v * v;
   }

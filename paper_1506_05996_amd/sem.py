@@ -118,6 +118,14 @@ def _check(status):
     return status
 
 
+def _no_alias(a, b, na, nb):
+    """Reject two tensors whose storage ranges overlap (the library forbids it)."""
+    a0, b0 = a.data_ptr(), b.data_ptr()
+    a1, b1 = a0 + a.numel() * a.element_size(), b0 + b.numel() * b.element_size()
+    if a0 < b1 and b0 < a1:
+        raise ValueError(f"{na} and {nb} must not overlap")
+
+
 def _ptr(a: np.ndarray):
     return ctypes.c_void_p(a.ctypes.data)
 
@@ -162,6 +170,7 @@ class Mesh:
         _check(_lib.sem_mesh_sizes(h, ctypes.byref(ng), ctypes.byref(nl), ctypes.byref(nv)))
         self.n_global, self.n_local, self.n_vertices = ng.value, nl.value, nv.value
         self.host_only = host_only
+        self.device = int(device)
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -231,20 +240,36 @@ class Mesh:
             return SEM_F32
         raise TypeError("vectors must be float64 or float32")
 
-    def _check_vec(self, t, n=None):
+    def _check_vecs(self, *specs):
+        """specs: (tensor, name, dtype or None, length or None).  Each must be a
+        contiguous 1D tensor of `length` entries (default n_global) on this
+        handle's device, float64 or float32 (or exactly `dtype`).  Types are
+        checked for every argument first, then sizes and devices; TypeError /
+        ValueError are raised before anything reaches the library."""
         import torch
-        n = self.n_global if n is None else n
-        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
-            raise ValueError(f"expected a contiguous device tensor of {n} entries")
+        for t, name, dtype, _ in specs:
+            if not isinstance(t, torch.Tensor):
+                raise TypeError(f"{name} must be a torch tensor")
+            if dtype is not None and t.dtype != dtype:
+                raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+            if t.dtype not in (torch.float64, torch.float32):
+                raise TypeError(f"{name} must be float64 or float32, got {t.dtype}")
+        for t, name, _, n in specs:
+            n = self.n_global if n is None else n
+            if not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"{name} must be a contiguous tensor of {n} entries")
+            if not t.is_cuda or t.device.index != self.device:
+                raise ValueError(f"{name} must live on cuda:{self.device}")
+
+    def _check_vec(self, t, n=None, dtype=None, name="vector"):
+        self._check_vecs((t, name, dtype, n))
 
     def apply_A(self, u, y=None, stream=None):
         import torch
-        self._check_vec(u)
         if y is None:
-            y = torch.empty_like(u)
-        self._check_vec(y)
-        if y.dtype != u.dtype:
-            raise TypeError("u and y must share a dtype")
+            y = torch.empty_like(u) if isinstance(u, torch.Tensor) else None
+        self._check_vecs((u, "u", None, None), (y, "y", getattr(u, "dtype", None), None))
+        _no_alias(u, y, "u", "y")
         _check(_lib.sem_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), _stream(stream)))
         return y
 
@@ -265,8 +290,8 @@ class Mesh:
 
     def time_apply_A(self, u, y, reps, stream=None):
         """Mean (element kernel, gather kernel) durations in ms over `reps` applies."""
-        self._check_vec(u)
-        self._check_vec(y)
+        self._check_vecs((u, "u", None, None), (y, "y", getattr(u, "dtype", None), None))
+        _no_alias(u, y, "u", "y")
         te, tg = ctypes.c_double(), ctypes.c_double()
         _check(_lib.sem_time_apply_A(self._h, _dptr(u), _dptr(y), self._dtype_code(u), int(reps), _stream(stream),
                                      ctypes.byref(te), ctypes.byref(tg)))
@@ -274,18 +299,18 @@ class Mesh:
 
     def precond(self, r, z=None, pc=PC_TWOSCALE, stream=None):
         import torch
-        self._check_vec(r)
         if z is None:
-            z = torch.empty_like(r)
-        self._check_vec(z)
+            z = torch.empty_like(r) if isinstance(r, torch.Tensor) else None
+        self._check_vecs((r, "r", None, None), (z, "z", getattr(r, "dtype", None), None))
+        _no_alias(r, z, "r", "z")
         _check(_lib.sem_precond(self._h, _dptr(r), _dptr(z), self._dtype_code(r), int(pc), _stream(stream)))
         return z
 
     def coarse_solve(self, R, Z=None, stream=None):
         import torch
-        self._check_vec(R, self.n_vertices)
         if Z is None:
-            Z = torch.empty_like(R)
+            Z = torch.empty_like(R) if isinstance(R, torch.Tensor) else None
+        self._check_vecs((R, "R", torch.float64, self.n_vertices), (Z, "Z", torch.float64, self.n_vertices))
         _check(_lib.sem_coarse_solve(self._h, _dptr(R), _dptr(Z), _stream(stream)))
         return Z
 
@@ -364,16 +389,14 @@ class Mesh:
         """One backward Euler step of the heat equation: (kappa A + M/dt) u_next =
         M (u_prev/dt + q), started from u_prev.  Returns (u_next, info)."""
         import torch
-        self._check_vec(u_prev)
-        if u_prev.dtype != torch.float64:
-            raise TypeError("u_prev must be float64")
-        if q is not None:
-            self._check_vec(q)
-            if q.dtype != torch.float64:
-                raise TypeError("q must be float64")
         if u_next is None:
-            u_next = torch.empty_like(u_prev)
-        self._check_vec(u_next)
+            u_next = torch.empty_like(u_prev) if isinstance(u_prev, torch.Tensor) else None
+        specs = [(u_prev, "u_prev", torch.float64, None), (u_next, "u_next", torch.float64, None)]
+        if q is not None:
+            specs.append((q, "q", torch.float64, None))
+        self._check_vecs(*specs)
+        if q is not None:
+            _no_alias(q, u_next, "q", "u_next")
         opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
                                   max_outer=max_outer, check_every=check_every, use_x0=1)
         st = SolveStats()
@@ -389,11 +412,10 @@ class Mesh:
     def solve(self, b, x=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-8, max_iter=1000, inner_rtol=1e-3,
               max_outer=20, check_every=1, use_x0=False, history=0, stream=None, raise_on_noconv=True):
         import torch
-        self._check_vec(b)
-        if b.dtype != torch.float64:
-            raise TypeError("b must be float64")
         if x is None:
-            x = torch.zeros_like(b)
+            x = torch.zeros_like(b) if isinstance(b, torch.Tensor) else None
+        self._check_vecs((b, "b", torch.float64, None), (x, "x", torch.float64, None))
+        _no_alias(b, x, "b", "x")
         opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
                                   max_outer=max_outer, check_every=check_every, use_x0=int(use_x0))
         st = SolveStats()
@@ -430,6 +452,7 @@ class Batch:
         opts = SetupOpts(device=device, host_only=0, build_fp32=int(build_fp32), autotune=int(autotune),
                          tune_cache=tune_cache.encode() if tune_cache else None)
         h = ctypes.c_void_p()
+        self.device = int(device)
         _check(_lib.sem_batch_setup(n, ctypes.cast(vp, _p), ctypes.cast(nv, _p), ctypes.cast(hp, _p),
                                     ctypes.cast(nh, _p), ctypes.cast(orders, _p), ctypes.byref(opts),
                                     ctypes.byref(h)))
@@ -454,10 +477,18 @@ class Batch:
             raise ValueError("one right-hand side per instance")
         if xs is None:
             xs = [torch.zeros_like(b) for b in bs]
+        if len(xs) != self.n:
+            raise ValueError("one solution vector per instance")
         bp, xp = (ctypes.c_void_p * self.n)(), (ctypes.c_void_p * self.n)()
         for i, (b, x) in enumerate(zip(bs, xs)):
-            if b.dtype != torch.float64 or not b.is_cuda or b.numel() != self.n_global[i]:
-                raise ValueError(f"instance {i}: expected a float64 device vector of {self.n_global[i]}")
+            for name, t in (("b", b), ("x", x)):
+                if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+                    raise TypeError(f"instance {i}: {name} must be a float64 tensor")
+                if (not t.is_cuda or t.device.index != self.device or not t.is_contiguous()
+                        or t.numel() != self.n_global[i]):
+                    raise ValueError(f"instance {i}: {name} must be a contiguous float64 vector of "
+                                     f"{self.n_global[i]} entries on cuda:{self.device}")
+            _no_alias(b, x, f"b[{i}]", f"x[{i}]")
             bp[i], xp[i] = b.data_ptr(), x.data_ptr()
         opts = default_solve_opts(mode=mode, pc=pc, rtol=rtol, max_iter=max_iter, inner_rtol=inner_rtol,
                                   max_outer=max_outer, check_every=check_every)

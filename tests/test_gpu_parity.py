@@ -161,10 +161,47 @@ def test_solve_edge_cases():
     x, info = M.solve(b, max_iter=1, raise_on_noconv=False)
     assert info["status"] == sem.SEM_ENOCONV and info["iterations"] == 1
     bn = b.clone()
-    bn[5] = float("nan")
+    free = np.nonzero(P.num.dirichlet == 0)[0]
+    bn[int(free[0])] = float("nan")
+    xn = torch.zeros_like(b)
     with pytest.raises(sem.SemError) as e:
-        M.solve(bn)
+        M.solve(bn, x=xn)
     assert e.value.status == sem.SEM_EBREAKDOWN
+    assert torch.isfinite(xn).all()
+
+
+def test_solve_start_dirichlet_values_and_argument_checks():
+    """A start that already meets the tolerance returns after 0 iterations with
+    x unchanged; values of b on the Dirichlet set take no part in the solve;
+    the binding rejects overlapping or mistyped vectors before any launch."""
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(3, perturb=0.1, seed=5)
+    M = sem.Mesh(m.vtx, m.hex, 4)
+    P = Problem(m.vtx, m.hex, 4)
+    b = torch.tensor(P.load(meshgen.manufactured_s), device=dev)
+    x, _ = M.solve(b, rtol=1e-12)
+    for mode in (sem.SOLVE_FP64, sem.SOLVE_FP32_REFINED):
+        x0 = x.clone()
+        x1, info = M.solve(b, x=x0, use_x0=True, rtol=1e-8, mode=mode)
+        assert info["iterations"] == 0 and torch.equal(x1, x)
+    dirty = b.clone()
+    dirty[torch.tensor(P.num.dirichlet.astype(bool), device=dev)] = 3.0
+    for mode in (sem.SOLVE_FP64, sem.SOLVE_FP32_REFINED):
+        xa, ia = M.solve(b, rtol=1e-10, mode=mode)
+        xb, ib = M.solve(dirty, rtol=1e-10, mode=mode)
+        assert torch.equal(xa, xb) and ia["iterations"] == ib["iterations"]
+    u = torch.rand(M.n_global, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        M.apply_A(u, u)
+    with pytest.raises(ValueError):
+        M.solve(b, x=b)
+    with pytest.raises(TypeError):
+        M.precond(u, torch.empty(M.n_global, dtype=torch.float32, device=dev))
+    with pytest.raises(TypeError):
+        M.solve(b, x=torch.zeros(M.n_global, dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):
+        M.solve(b, x=torch.zeros(M.n_global - 1, dtype=torch.float64, device=dev))
 
 
 def test_custom_dirichlet_set():

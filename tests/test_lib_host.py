@@ -288,3 +288,48 @@ def test_coarse_factor_size_bounds(k):
     assert nc <= fwd - bwd <= nc * nc
     if k == 2:
         assert (fwd, bwd) == (1, 0)
+
+
+def test_binding_rejects_bad_vectors_before_any_call():
+    """Every vector argument is checked in the binding (type, dtype, size,
+    device) before a pointer reaches the library; overlapping buffers are
+    rejected.  Host tensors stand in for device ones here: the dtype checks come
+    first, then the device check."""
+    torch = pytest.importorskip("torch")
+    m = meshgen.cube_mesh(2)
+    M = sem.Mesh(m.vtx, m.hex, 2, host_only=True)
+    ng, nv = M.n_global, M.n_vertices
+    f64, f32 = torch.zeros(ng, dtype=torch.float64), torch.zeros(ng, dtype=torch.float32)
+    with pytest.raises(TypeError):
+        M.apply_A(f64, f32)
+    with pytest.raises(TypeError):
+        M.apply_A(torch.zeros(ng, dtype=torch.int64))
+    with pytest.raises(TypeError):
+        M.precond(f64, torch.zeros(ng, dtype=torch.float32))
+    with pytest.raises(TypeError):
+        M.solve(f32)
+    with pytest.raises(TypeError):
+        M.solve(f64, torch.zeros(ng, dtype=torch.float32))
+    with pytest.raises(TypeError):
+        M.coarse_solve(torch.zeros(nv, dtype=torch.float32))
+    with pytest.raises(TypeError):
+        M.heat_step(f64, 0.1, 1.0, u_next=f32)
+    with pytest.raises(TypeError):
+        M.apply_A(np.zeros(ng))
+    with pytest.raises(ValueError):
+        M.apply_A(torch.zeros(ng + 1, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        M.solve(f64)  # a host tensor: not on the handle's device
+    with pytest.raises(ValueError):
+        M.apply_A(torch.zeros(2 * ng, dtype=torch.float64)[::2])  # not contiguous
+    M.close()
+
+
+def test_overlap_check():
+    torch = pytest.importorskip("torch")
+    buf = torch.zeros(100, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        sem._no_alias(buf[:60], buf[50:], "a", "b")
+    with pytest.raises(ValueError):
+        sem._no_alias(buf, buf, "a", "b")
+    sem._no_alias(buf[:50], buf[50:], "a", "b")  # adjacent, disjoint
