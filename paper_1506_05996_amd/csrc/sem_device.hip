@@ -112,6 +112,14 @@ const float* CEp<float>(sem_mesh m) { return m->ce32.p; }
 constexpr int kTileCandidates[4] = {1, 2, 4, 8};
 constexpr int kTileMfma = 16;
 constexpr int kTileGeo = 32;  // factors rebuilt from the vertices, default elements per workgroup
+// the line-phase kernel: factors rebuilt from the vertices, or stored
+constexpr int kTileLineGeo = 64;
+constexpr int kTileLineStored = 48;
+
+bool tile_code_ok(int epb, int N) {
+  if (epb == 1 || epb == 2 || epb == 4 || epb == 8) return epb * (N + 1) * (N + 1) <= 1024;
+  return epb == kTileGeo || epb == kTileLineGeo || epb == kTileLineStored || (epb == kTileMfma && N == 15);
+}
 
 template <int N>
 constexpr bool tile_ok(int epb) {
@@ -181,6 +189,18 @@ int64_t launch_ax_tile(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t 
   }
 }
 
+template <int N, typename T, bool GEO, bool KN = false>
+int64_t launch_ax_line(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
+  constexpr int EPB = ax_epb<N>();
+  const HostTables& T_ = m->T;
+  const int64_t grid = xcd_grid((T_.E + EPB - 1) / EPB);
+  hipLaunchKernelGGL((ax_line_kernel<N, T, EPB, GEO, KN>), dim3((unsigned)grid), dim3(EPB * (N + 1) * (N + 1)), 0, s,
+                     u, y, Wp<T>(m), GEO ? X8p<T>(m) : Gp<T>(m), m->rec.p, Dp<T>(m), m->dir.p, m->order.p, T_.E, dpart,
+                     TQp<T>(m), op_coef<T>(m));
+  SEM_HIP(hipGetLastError());
+  return grid;
+}
+
 template <int N, typename T>
 int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
   const int epb = m->epb[std::is_same<T, double>::value ? 0 : 1];
@@ -201,6 +221,11 @@ int64_t launch_ax(sem_mesh m, const T* u, T* y, double* dpart, hipStream_t s) {
     if (m->per_node) return launch_ax_tile<N, T, ax_epb<N>(), true, true>(m, u, y, dpart, s);
     return launch_ax_tile<N, T, ax_epb<N>(), true>(m, u, y, dpart, s);
   }
+  if (epb == kTileLineGeo) {
+    if (m->per_node) return launch_ax_line<N, T, true, true>(m, u, y, dpart, s);
+    return launch_ax_line<N, T, true>(m, u, y, dpart, s);
+  }
+  if (epb == kTileLineStored) return launch_ax_line<N, T, false>(m, u, y, dpart, s);
   switch (epb > 0 ? epb : ax_epb<N>()) {
     case 1: return launch_ax_tile<N, T, 1>(m, u, y, dpart, s);
     case 2: return launch_ax_tile<N, T, 2>(m, u, y, dpart, s);
@@ -1249,6 +1274,8 @@ int tune_tile(sem_mesh m) {
     if (c * (N + 1) * (N + 1) <= 1024 && c * (N + 1) * (N + 1) >= 16) cands.push_back(c);
   if (N == 15) cands.push_back(kTileMfma);
   cands.push_back(kTileGeo);
+  cands.push_back(kTileLineGeo);
+  cands.push_back(kTileLineStored);
   if (cands.size() <= 1) return cands.empty() ? 1 : cands[0];
   DBuf<T> u, y;
   u.alloc(m->T.n_global);
@@ -1311,8 +1338,7 @@ void autotune(sem_mesh m, const char* cache) {
         std::fclose(f);
       }
     }
-    if (found == 1 || found == 2 || found == 4 || found == 8 || found == kTileGeo ||
-        (found == kTileMfma && m->T.N == 15)) {
+    if (found > 0 && tile_code_ok(found, m->T.N)) {
       m->epb[d] = found;
       continue;
     }
@@ -1372,11 +1398,7 @@ void sem_default_setup_opts(sem_setup_opts* o) {
 
 int sem_mesh_set_tile(sem_mesh m, int dtype, int epb) {
   if (!m || (dtype != SEM_F64 && dtype != SEM_F32)) return SEM_EINVAL;
-  const int N = m->T.N;
-  const bool ok = (epb == 1 || epb == 2 || epb == 4 || epb == 8)
-                      ? epb * (N + 1) * (N + 1) <= 1024
-                      : (epb == kTileGeo || (epb == kTileMfma && N == 15));
-  if (!ok) {
+  if (!tile_code_ok(epb, m->T.N)) {
     set_error("tile not available for this order and dtype");
     return SEM_EINVAL;
   }

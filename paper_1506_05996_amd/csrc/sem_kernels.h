@@ -359,6 +359,213 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Operator kernel by line phases, eq. (R) / Algorithm 2.  Each 1D contraction
+// is done by lanes that own whole lines of the element, so the derivative
+// matrix is wave-uniform (scalar registers) and every line is read from LDS
+// once per contraction instead of once per output node:
+//   eta lines    (lane (i, k)):  u_s = D u along eta          -> Z
+//   xi lines     (lane (j, k)):  u_r = D u along xi, in place -> X
+//   pencils      (lane (i, j)):  u_t = D u along zeta in registers; the factors
+//                G (stored, or rebuilt from the vertices); A -> X, B -> Z in
+//                place; the zeta part of the transposed sum D^T C in registers
+//   xi, eta lines: D^T A along xi in place in X, D^T B along eta in place in Z
+//   pencils:     result = zeta part + X + Z at the lane's nodes
+// Two padded LDS buffers per element (line stride N + 2, plane stride
+// (N + 1)(N + 2)); lanes of one element read distinct banks along all three
+// directions.  Same arguments, results and epilogue as ax_kernel.
+// ---------------------------------------------------------------------------
+template <int N, typename T, int EPB, bool GEO = false, bool KN = false>
+__global__ void __launch_bounds__(EPB*(N + 1) * (N + 1))
+__attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 1, 8)))
+ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T* __restrict__ G,
+               const int32_t* __restrict__ rec, const T* __restrict__ Dg, const uint8_t* __restrict__ dir,
+               const int32_t* __restrict__ order, int64_t E, double* __restrict__ dpart, const T* __restrict__ tq,
+               OpCoef<T> oc) {
+  constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
+  constexpr int LS = n1 + 1, PS = n1 * LS, BS = n1 * PS;
+  __shared__ T sX[EPB][BS];
+  __shared__ T sZ[EPB][BS];
+  __shared__ double sRed[EPB * P];
+  const int tid = threadIdx.x;
+  const int le = tid / P, ij = tid - le * P;
+  const int a = ij % n1, b = ij / n1;  // pencil (i, j) = (a, b); lines (., k = b)
+  const int64_t pos = xcd_position(blockIdx.x, (E + EPB - 1) / EPB) * EPB + le;
+  const bool valid = pos < E;
+  const int64_t e = valid ? order[pos] : 0;
+  const int cx = node_class(a, N), cy = node_class(b, N);
+  const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+  const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
+  const T* Ge = G + (GEO ? e * 24 : e * 6 * NN + ij);
+  T P0[3], P1[3], Q0[3], Q1[3], C2[3], rij = 0;
+  if constexpr (GEO) {
+    const T ti = tq[a], tj = tq[b];
+    const T f0i = T(0.5) * (T(1) - ti), f1i = T(0.5) * (T(1) + ti);
+    const T f0j = T(0.5) * (T(1) - tj), f1j = T(0.5) * (T(1) + tj);
+    rij = tq[n1 + a] * tq[n1 + b];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      P0[q] = T(0.5) * ((Ge[1 * 3 + q] - Ge[0 * 3 + q]) * f0j + (Ge[3 * 3 + q] - Ge[2 * 3 + q]) * f1j);
+      P1[q] = T(0.5) * ((Ge[5 * 3 + q] - Ge[4 * 3 + q]) * f0j + (Ge[7 * 3 + q] - Ge[6 * 3 + q]) * f1j);
+      Q0[q] = T(0.5) * ((Ge[2 * 3 + q] - Ge[0 * 3 + q]) * f0i + (Ge[3 * 3 + q] - Ge[1 * 3 + q]) * f1i);
+      Q1[q] = T(0.5) * ((Ge[6 * 3 + q] - Ge[4 * 3 + q]) * f0i + (Ge[7 * 3 + q] - Ge[5 * 3 + q]) * f1i);
+      C2[q] = T(0.5) * ((Ge[4 * 3 + q] - Ge[0 * 3 + q]) * f0i * f0j + (Ge[5 * 3 + q] - Ge[1 * 3 + q]) * f1i * f0j +
+                        (Ge[6 * 3 + q] - Ge[2 * 3 + q]) * f0i * f1j + (Ge[7 * 3 + q] - Ge[3 * 3 + q]) * f1i * f1j);
+    }
+  }
+  T uv[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+    int ai, aj, ak;
+    unpack_coef(r.y, ai, aj, ak);
+    uv[k] = valid ? u[r.x + ai * a + aj * b + ak * k] : T(0);
+  }
+  T kv[KN ? n1 : 1];
+  if constexpr (KN) {
+#pragma unroll
+    for (int k = 0; k < n1; ++k) kv[k] = valid ? oc.kn[e * NN + k * P + ij] : T(1);
+  }
+  T* X = sX[le];
+  T* Z = sZ[le];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) X[k * PS + b * LS + a] = uv[k];
+  __syncthreads();
+  // Forward contractions loop over the output index q with row q of D in
+  // scalar registers (one row live at a time); the line sits in registers.
+  {  // eta lines: lane (i = a, k = b)
+    T v[n1];
+#pragma unroll
+    for (int m = 0; m < n1; ++m) v[m] = X[b * PS + m * LS + a];
+#pragma unroll 1
+    for (int q = 0; q < n1; ++q) {
+      const T* Dq = Dg + q * n1;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
+      Z[b * PS + q * LS + a] = s;
+    }
+  }
+  __syncthreads();
+  {  // xi lines: lane (j = a, k = b), in place
+    T v[n1];
+#pragma unroll
+    for (int m = 0; m < n1; ++m) v[m] = X[b * PS + a * LS + m];
+#pragma unroll 1
+    for (int q = 0; q < n1; ++q) {
+      const T* Dq = Dg + q * n1;
+      T s = 0;
+#pragma unroll
+      for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
+      X[b * PS + a * LS + q] = s;
+    }
+  }
+  __syncthreads();
+  T rw[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) rw[k] = T(0);
+#pragma unroll 1
+  for (int k = 0; k < n1; ++k) {
+    const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
+    T g0, g1, g2, g3, g4, g5;
+    if constexpr (GEO) {
+      const T tk = tq[k];
+      const T f0k = T(0.5) * (T(1) - tk), f1k = T(0.5) * (T(1) + tk);
+      T c0[3], c1[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        c0[q] = f0k * P0[q] + f1k * P1[q];
+        c1[q] = f0k * Q0[q] + f1k * Q1[q];
+      }
+      const T a0x = c1[1] * C2[2] - c1[2] * C2[1], a0y = c1[2] * C2[0] - c1[0] * C2[2], a0z = c1[0] * C2[1] - c1[1] * C2[0];
+      const T a1x = C2[1] * c0[2] - C2[2] * c0[1], a1y = C2[2] * c0[0] - C2[0] * c0[2], a1z = C2[0] * c0[1] - C2[1] * c0[0];
+      const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
+      const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
+      T sc = rij * tq[n1 + k] * recip_pos(det);
+      if constexpr (KN) sc *= pick(kv, k);
+      g0 = sc * (a0x * a0x + a0y * a0y + a0z * a0z);
+      g1 = sc * (a0x * a1x + a0y * a1y + a0z * a1z);
+      g2 = sc * (a0x * a2x + a0y * a2y + a0z * a2z);
+      g3 = sc * (a1x * a1x + a1y * a1y + a1z * a1z);
+      g4 = sc * (a1x * a2x + a1y * a2y + a1z * a2z);
+      g5 = sc * (a2x * a2x + a2y * a2y + a2z * a2z);
+    } else {
+      const T* Gk = Ge + k * P;
+      g0 = Gk[0 * NN];
+      g1 = Gk[1 * NN];
+      g2 = Gk[2 * NN];
+      g3 = Gk[3 * NN];
+      g4 = Gk[4 * NN];
+      g5 = Gk[5 * NN];
+    }
+    const int o = k * PS + b * LS + a;
+    const T ur = X[o], us = Z[o];
+    T ut = 0;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) ut += Dk[m] * uv[m];
+    const T A = g0 * ur + g1 * us + g2 * ut;
+    const T B = g1 * ur + g3 * us + g4 * ut;
+    const T C = g2 * ur + g4 * us + g5 * ut;
+    X[o] = A;
+    Z[o] = B;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) rw[m] += Dk[m] * C;
+  }
+  __syncthreads();
+  // Transposed contractions loop over the input index m: row m of D in scalar
+  // registers scales line entry m into all outputs; each lane owns its line,
+  // so the results overwrite it after the loop.
+  {  // transposed xi lines (lane (j = a, k = b)) and eta lines (lane (i = a, k = b)), in place
+    T sx[n1], sz[n1];
+#pragma unroll
+    for (int q = 0; q < n1; ++q) sx[q] = sz[q] = T(0);
+#pragma unroll 1
+    for (int m = 0; m < n1; ++m) {
+      const T* Dm = Dg + m * n1;
+      const T vx = X[b * PS + a * LS + m], vz = Z[b * PS + m * LS + a];
+#pragma unroll
+      for (int q = 0; q < n1; ++q) {
+        sx[q] += Dm[q] * vx;
+        sz[q] += Dm[q] * vz;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < n1; ++q) {
+      X[b * PS + a * LS + q] = sx[q];
+      Z[b * PS + q * LS + a] = sz[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < n1; ++k) rw[k] += X[k * PS + b * LS + a] + Z[k * PS + b * LS + a];
+  double dacc = 0.0;
+  if (valid) {
+    const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
+    const ElemCoef<T> ec = elem_coef(oc, e);
+#pragma unroll
+    for (int k = 0; k < n1; ++k) {
+      const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+      int ai, aj, ak;
+      unpack_coef(r.y, ai, aj, ak);
+      const int off = ai * a + aj * b + ak * k;
+      const T uk = uv[k];
+      const T v = elem_value(oc, ec, e, NN, k * P + ij, rw[k], uk);
+      if (r.w & kFlagInterior) {
+        const T yv = (masked_interior && dir[r.x + off]) ? T(0) : op_value(oc, v, r.x + off, uk);
+        y[r.x + off] = yv;
+        dacc += (double)uk * (double)yv;
+      } else {
+        w[r.z + off] = v;
+      }
+    }
+  }
+  if (dpart != nullptr) {
+    const double t = group_sum<EPB * P>(dacc, sRed);
+    if (tid == 0) dpart[blockIdx.x] = t;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Operator at N = 15 on matrix cores (v_mfma_f64_16x16x4f64 in FP64,
 // v_mfma_f32_16x16x4_f32 in FP32: the same operand layout).  One

@@ -100,6 +100,9 @@ _lib.sem_mesh_set_tile.argtypes = [_p, ctypes.c_int, ctypes.c_int]
 TILE_MFMA = 16
 COARSE_EXACT, COARSE_AMG = 0, 1  # sem_coarse_solver
 TILE_GEO = 32  # operator tile that rebuilds the geometric factors from the vertices
+TILE_LINE_GEO = 64  # line-phase operator kernel, factors rebuilt from the vertices
+TILE_LINE = 48  # line-phase operator kernel, stored factors
+TILE_MFMA = 16  # matrix-core operator kernel (N = 15)
 
 
 class SemError(RuntimeError):

@@ -49,7 +49,7 @@ def test_element_coefficients(name, kw, N):
     P = Problem(m.vtx, m.hex, N, kappa=kap, c=c)
     M.set_element_coefficients(kap, c)
     u = rng.uniform(-1, 1, M.n_global)
-    tiles = [None] + ([sem.TILE_GEO] if N <= 9 else []) + ([16] if N == 15 else [])
+    tiles = [None] + ([sem.TILE_GEO, sem.TILE_LINE_GEO, sem.TILE_LINE] if N <= 9 else []) + ([16] if N == 15 else [])
     for tile in tiles:
         if tile is not None:
             M.set_tile(tile)
@@ -102,13 +102,13 @@ def test_node_coefficients(name, kw, N):
     assert np.array_equal(M.geometry()[0], G0)  # the host keeps the plain factors
     u = rng.uniform(-1, 1, M.n_global)
     yo = P.A(u)
-    tiles = [None] + ([sem.TILE_GEO] if N <= 9 else []) + ([16] if N == 15 else [])
+    tiles = [None] + ([sem.TILE_GEO, sem.TILE_LINE_GEO, sem.TILE_LINE] if N <= 9 else []) + ([16] if N == 15 else [])
     for tile in tiles:
         if tile is not None:
             M.set_tile(tile)
         y = M.apply_A(torch.tensor(u, device=dev)).cpu().numpy()
         assert rel_l2(y, yo) <= 1e-12, tile
-    for tile in [None] + ([sem.TILE_GEO] if N <= 9 else []) + ([16] if N == 15 else []):
+    for tile in [None] + ([sem.TILE_GEO, sem.TILE_LINE_GEO, sem.TILE_LINE] if N <= 9 else []) + ([16] if N == 15 else []):
         if tile is not None:
             M.set_tile(tile, dtype=sem.SEM_F32)
         y32 = M.apply_A(torch.tensor(u, device=dev, dtype=torch.float32)).double().cpu().numpy()

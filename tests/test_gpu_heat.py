@@ -57,7 +57,7 @@ def test_operator_and_precond_with_coefficients(case, kc):
     M.set_coefficients(kappa, c)
     assert M.coefficients() == (kappa, c)
     u = np.random.default_rng(20).uniform(-1, 1, M.n_global)
-    tiles = [None] + ([sem.TILE_GEO] if N <= 9 else []) + ([16] if N == 15 else [])
+    tiles = [None] + ([sem.TILE_GEO, sem.TILE_LINE_GEO, sem.TILE_LINE] if N <= 9 else []) + ([16] if N == 15 else [])
     for tile in tiles:
         if tile is not None:
             M.set_tile(tile)
