@@ -202,6 +202,26 @@ int sem_pcg_solve(sem_mesh m, const double* b_dev, double* x_dev, const sem_solv
                   sem_solve_stats* st, void* stream);
 
 /*
+ * sem_pcg_solve_noalloc -- sem_pcg_solve for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, hosts that
+ * forbid allocation after start-up).  Same arguments, results and statuses as
+ * sem_pcg_solve; the work vectors, partial sums and scalars of the solve live
+ * in one static device array of the library (128 MiB per device, held until
+ * the process ends) instead of the handle's lazily allocated buffers, and the
+ * call allocates nothing.  Needed: 40 bytes per global node (FP64), 60 with
+ * SEM_SOLVE_FP32_REFINED, plus about 8 bytes per element (about 3.3 M and 2.2 M global nodes at
+ * most); a larger mesh gives SEM_EINVAL and a message naming both sizes,
+ * before any device work.  Everything the solve reads is built at set-up (the
+ * coarse-solve graph, the side stream); if a later call on the handle dropped
+ * one of them, the call fails with SEM_EINVAL instead of rebuilding it.  All
+ * calls on one device share the array: calls that overlap in time on one
+ * device (two host threads, or two streams) race and give wrong results.  Each
+ * solve initialises the parts it reads; contents are not kept between calls.
+ */
+int sem_pcg_solve_noalloc(sem_mesh m, const double* b_dev, double* x_dev, const sem_solve_opts* o,
+                          sem_solve_stats* st, void* stream);
+
+/*
  * sem_mesh_set_coefficients -- constant kappa > 0 and c >= 0 of the model
  * problem c u - div(kappa grad u) = s (eq. (pde)).  Afterwards sem_apply_A
  * computes kappa times the stiffness action plus c m_N u (the GLL mass is

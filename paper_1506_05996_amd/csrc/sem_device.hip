@@ -10,6 +10,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "sem_device.h"
@@ -857,6 +858,73 @@ void ensure_work(sem_mesh m, bool need32) {
   m->wk.dpart = m->dpart.p;
 }
 
+// --- static scratch of sem_pcg_solve_noalloc ------------------------------
+// The work of one solve (Algorithm 1's scalars, partial sums and the five FP64
+// vectors, plus five FP32 vectors for the refined form) as views into one
+// file-scope device array, for callers that cannot allocate device memory.
+// Every device holds its own copy of the array, at its own address, resolved
+// once per device at set-up (create_mesh) with that device current; host code
+// uses only that address, never the array's name.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_dev;  // by device id: the device address of scratch (NULL until resolved)
+
+void resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_dev.size() <= device) g_scratch_dev.resize((size_t)device + 1, nullptr);
+  if (g_scratch_dev[device] != nullptr) return;
+  void* p = nullptr;
+  SEM_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (p == nullptr) throw Error{SEM_EHIP, "hipGetSymbolAddress(scratch) returned NULL"};
+  g_scratch_dev[device] = static_cast<double*>(p);
+}
+
+double* scratch_of(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return device >= 0 && device < (int)g_scratch_dev.size() ? g_scratch_dev[device] : nullptr;
+}
+
+// byte offsets of one solve's work inside the scratch array (256-aligned parts)
+struct ScratchLayout {
+  size_t sc, part, dpart, v64, v32, total;
+};
+
+ScratchLayout scratch_layout(sem_mesh m, bool need32) {
+  auto up = [](size_t bytes) { return (bytes + 255) / 256 * 256; };
+  const size_t n = (size_t)m->T.n_global;
+  ScratchLayout L{};
+  size_t o = 0;
+  L.sc = o;
+  o += up(16 * sizeof(double));
+  L.part = o;
+  o += up(kRedBlocks * sizeof(double));
+  L.dpart = o;
+  o += up(dpart_count(m) * sizeof(double));
+  L.v64 = o;
+  o += 5 * up(n * sizeof(double));
+  L.v32 = o;
+  if (need32) o += 5 * up(n * sizeof(float));
+  L.total = o;
+  return L;
+}
+
+// the next solve's work as views into the scratch array at `base`
+void scratch_work(sem_mesh m, bool need32, double* base) {
+  const ScratchLayout L = scratch_layout(m, need32);
+  const size_t n = (size_t)m->T.n_global;
+  char* c = reinterpret_cast<char*>(base);
+  const size_t s64 = (n * sizeof(double) + 255) / 256 * 256, s32 = (n * sizeof(float) + 255) / 256 * 256;
+  for (int q = 0; q < 5; ++q) {
+    m->wk.v64[q] = reinterpret_cast<double*>(c + L.v64 + q * s64);
+    m->wk.v32[q] = need32 ? reinterpret_cast<float*>(c + L.v32 + q * s32) : nullptr;
+  }
+  m->wk.part = reinterpret_cast<double*>(c + L.part);
+  m->wk.sc = reinterpret_cast<double*>(c + L.sc);
+  m->wk.dpart = reinterpret_cast<double*>(c + L.dpart);
+}
+
 template <typename TA, typename TB>
 void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s) {
   const int64_t n = m->T.n_global;
@@ -1373,6 +1441,7 @@ sem_mesh_s* create_mesh(const double* vtx, int64_t n_vtx, const int64_t* hex, in
   m->epb[0] = m->epb[1] = default_tile(order);
   if (!m->host_only) {
     upload_all(m.get());
+    resolve_scratch(m->device);  // upload_all left the handle's device current
     if (opts->autotune) autotune(m.get(), opts->tune_cache);
   }
   return m.release();
@@ -1655,6 +1724,47 @@ int sem_pcg_solve(sem_mesh m, const double* b, double* x, const sem_solve_opts* 
     SEM_HIP(hipSetDevice(m->device));
     if (o->mode == SEM_SOLVE_FP32_REFINED && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
     ensure_work(m, o->mode == SEM_SOLVE_FP32_REFINED);
+    return solve_impl(m, b, x, o, st, (hipStream_t)stream);
+  });
+}
+
+int sem_pcg_solve_noalloc(sem_mesh m, const double* b, double* x, const sem_solve_opts* o, sem_solve_stats* st,
+                          void* stream) {
+  if (!m) {
+    set_error("NULL handle");
+    return SEM_EINVAL;
+  }
+  if (!b || !x || b == x) return SEM_EINVAL;
+  sem_solve_opts d;
+  sem_default_solve_opts(&d);
+  if (!o) o = &d;
+  if (o->pc < 0 || o->pc > 3 || o->max_iter < 0 || !(o->rtol >= 0.0)) return SEM_EINVAL;
+  const bool need32 = o->mode == SEM_SOLVE_FP32_REFINED;
+  const size_t need = scratch_layout(m, need32).total;
+  if (need > kScratchBytes) {
+    set_error("sem_pcg_solve_noalloc: this mesh needs " + std::to_string(need) + " bytes of static scratch, more than " +
+              "its maximum of " + std::to_string(kScratchBytes) + " bytes; use sem_pcg_solve");
+    return SEM_EINVAL;
+  }
+  int s0 = need_device(m);
+  if (s0) return s0;
+  return guarded([&]() -> int {
+    SEM_HIP(hipSetDevice(m->device));
+    if (need32 && !m->fp32) throw Error{SEM_EUNSUPPORTED, "handle built without FP32 copies"};
+    double* base = scratch_of(m->device);
+    if (base == nullptr) throw Error{SEM_EHIP, "static scratch not resolved on this device"};
+    // views into the scratch for this solve only; any lazy set-up that would
+    // allocate raises instead (no_alloc); the handle's own buffers return with
+    // the next sem_pcg_solve
+    struct Restore {
+      sem_mesh m;
+      ~Restore() {
+        m->no_alloc = false;
+        m->wk = sem_mesh_s::SolveWork{};
+      }
+    } restore{m};
+    m->no_alloc = true;
+    scratch_work(m, need32, base);
     return solve_impl(m, b, x, o, st, (hipStream_t)stream);
   });
 }

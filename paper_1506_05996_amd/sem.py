@@ -38,7 +38,7 @@ EXPORTS = [
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_mesh_coarse_factor_size", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
     "sem_mesh_set_element_coefficients", "sem_mesh_set_node_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
-    "sem_mesh_amg_hierarchy",
+    "sem_mesh_amg_hierarchy", "sem_pcg_solve_noalloc",
 ]
 
 
@@ -78,6 +78,7 @@ _lib.sem_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, _p]
 _lib.sem_precond.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p]
 _lib.sem_coarse_solve.argtypes = [_p, _p, _p, _p]
 _lib.sem_pcg_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
+_lib.sem_pcg_solve_noalloc.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
 _lib.sem_time_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
 _lib.sem_last_error.restype = ctypes.c_char_p
@@ -413,7 +414,10 @@ class Mesh:
         return u_next, info
 
     def solve(self, b, x=None, mode=SOLVE_FP64, pc=PC_TWOSCALE, rtol=1e-8, max_iter=1000, inner_rtol=1e-3,
-              max_outer=20, check_every=1, use_x0=False, history=0, stream=None, raise_on_noconv=True):
+              max_outer=20, check_every=1, use_x0=False, history=0, stream=None, raise_on_noconv=True,
+              noalloc=False):
+        """sem_pcg_solve, or with noalloc=True sem_pcg_solve_noalloc (work in the
+        library's static scratch array; pass x to keep this call free of allocation)."""
         import torch
         if x is None:
             x = torch.zeros_like(b) if isinstance(b, torch.Tensor) else None
@@ -427,8 +431,8 @@ class Mesh:
             hist = (ctypes.c_double * history)()
             st.history = hist
             st.history_cap = history
-        status = _lib.sem_pcg_solve(self._h, _dptr(b), _dptr(x), ctypes.byref(opts), ctypes.byref(st),
-                                    _stream(stream))
+        fn = _lib.sem_pcg_solve_noalloc if noalloc else _lib.sem_pcg_solve
+        status = fn(self._h, _dptr(b), _dptr(x), ctypes.byref(opts), ctypes.byref(st), _stream(stream))
         info = dict(status=status, iterations=st.iterations, outer=st.outer_iterations,
                     rel_residual=st.rel_residual, solve_ms=st.solve_ms,
                     history=list(hist[:st.history_len]) if hist is not None else None)

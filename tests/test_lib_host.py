@@ -333,3 +333,25 @@ def test_overlap_check():
     with pytest.raises(ValueError):
         sem._no_alias(buf, buf, "a", "b")
     sem._no_alias(buf[:50], buf[50:], "a", "b")  # adjacent, disjoint
+
+
+def test_noalloc_solve_rejects_meshes_beyond_its_scratch():
+    """sem_pcg_solve_noalloc checks its static scratch (128 MiB) before any
+    device work: 2,571,353 global nodes fit at 40 bytes per node (FP64; a
+    host-only handle then reports that it has no device state) but not at 60
+    (FP32-refined: SEM_EINVAL naming both sizes)."""
+    m = meshgen.cube_mesh(17)
+    M = sem.Mesh(m.vtx, m.hex, 8, host_only=True)
+    assert M.n_global == 137 ** 3
+    lib = ctypes.CDLL(sem.LIB_PATH)
+    fn = lib.sem_pcg_solve_noalloc
+    fn.argtypes = [ctypes.c_void_p] * 3 + [ctypes.POINTER(sem.SolveOpts), ctypes.POINTER(sem.SolveStats),
+                                           ctypes.c_void_p]
+    st = sem.SolveStats()
+    b, x = ctypes.c_void_p(256), ctypes.c_void_p(512)
+    o64 = sem.default_solve_opts(mode=sem.SOLVE_FP64)
+    assert fn(M.handle, b, x, ctypes.byref(o64), ctypes.byref(st), None) == sem.SEM_EUNSUPPORTED
+    o32 = sem.default_solve_opts(mode=sem.SOLVE_FP32_REFINED)
+    assert fn(M.handle, b, x, ctypes.byref(o32), ctypes.byref(st), None) == sem.SEM_EINVAL
+    msg = sem.last_error()
+    assert "static scratch" in msg and str(128 << 20) in msg
