@@ -17,6 +17,14 @@ FP32-refined form: one untimed warm-up solve per form, then the median of
 face (`coefficients`), and the heat-equation run (Section 6.2) on a
 synthetic rod of 62,500 hexahedra at N = 7: 70 backward Euler steps, each a
 PCG solve to 1e-10, in FP64 and FP32-refined form (`heat` in the output).
+Further sections of the same line: `stream` (the device's copy/triad/read
+bandwidth with the library's own streaming kernels), `box20x8_N15` (20^3
+hexahedra stretched 8:1, N = 15: the FP64 and FP32 matrix-core operators
+against the vector kernel, PCG in FP64 and FP32-refined form), `batch64` (64
+instances of orders 3..8 solved in one batched call against one by one) and
+`cube4_N4` (the small cube: FP64 latency to 1e-8, the refined form to 1e-10
+with a sweep of its inner tolerance).  `cpu_baseline` times the FP64 oracle on
+the host: its operator on a sample of the 56^3 mesh, and its PCG.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -111,32 +119,111 @@ def traffic_from_counters(kernel):
     return c.get("bytes_per_apply")
 
 
-def cpu_baseline(mesh, N, n_global, budget_s=10.0, sample_elems=4096):
-    """The FP64 oracle's operator, timed on the host on a sample of the
-    workload's elements; scaled to GDOF/s of the full workload."""
+def host_info():
+    """Host description for the CPU baseline: model name, cores available to
+    this process, and a one-thread numpy triad a = b + 0.5 c over 3 x 256 MiB."""
     import numpy as np
 
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    n = 1 << 25
+    b, c = np.ones(n), np.full(n, 2.0)
+    a = np.empty(n)
+    best = 1e30
+    for _ in range(5):
+        t0 = time.perf_counter()
+        np.multiply(c, 0.5, out=a)
+        np.add(a, b, out=a)
+        best = min(best, time.perf_counter() - t0)
+    # multiply reads c, writes a; add reads a and b, writes a
+    return {"cpu_model": model, "nproc": cores, "triad_gbs_1thread": round(5 * 8 * n / best / 1e9, 2)}
+
+
+def cpu_baseline(mesh, N, n_global, gpu_pcg_iterations=None, budget_s=10.0, sample_elems=4096):
+    """The FP64 oracle timed on the host, one thread (numpy einsum and vector
+    operations; BLAS pinned to one thread): its operator on a sample of the
+    workload's elements, scaled to GDOF/s of the full workload; its PCG on the
+    4^3, N = 4 cube to 1e-8 in full; and one PCG iteration (operator, two-scale
+    preconditioner, vector updates) on a 12^3-hex sample of the 56^3, N = 7
+    workload, scaled by elements and by the GPU's FP64 iteration count to an
+    estimated time to 1e-10 at full size."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import meshgen
     from oracle.problem import Problem
 
-    S = min(sample_elems, mesh.n_elem)
-    P = Problem(mesh.vtx, mesh.hex[:S], N, fine=False, coarse=False)
-    u = np.random.default_rng(1507).uniform(-1, 1, P.num.n_global)
-    P.A(u)
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    with threadpool_limits(limits=1):
+        S = min(sample_elems, mesh.n_elem)
+        P = Problem(mesh.vtx, mesh.hex[:S], N, fine=False, coarse=False)
+        u = np.random.default_rng(1507).uniform(-1, 1, P.num.n_global)
         P.A(u)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    t = el / reps
-    t_full = t * mesh.n_elem / S
-    return {"value": n_global / t_full / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"oracle apply_A on the first {S} of {mesh.n_elem} elements of the same mesh "
-                      f"(N={N}), {reps} reps in {el:.1f} s, {t * 1e3:.1f} ms/apply, scaled by elements"}
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            P.A(u)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+        t = el / reps
+        t_full = t * mesh.n_elem / S
+        out = {"value": n_global / t_full / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle apply_A on the first {S} of {mesh.n_elem} elements of the same mesh "
+                         f"(N={N}), {reps} reps in {el:.1f} s, {t * 1e3:.1f} ms/apply, scaled by elements"}
+        # PCG, config 1 in full
+        m1, N1 = meshgen.workload_mesh("cube4_N4")
+        t0 = time.perf_counter()
+        P1 = Problem(m1.vtx, m1.hex, N1)
+        b1 = P1.load(lambda x: meshgen.manufactured_s(x, m1.lengths))
+        t1 = time.perf_counter()
+        _, it1, _, _ = P1.solve(b1, rtol=1e-8)
+        t2 = time.perf_counter()
+        out["pcg_cube4_N4"] = {"setup_s": round(t1 - t0, 3), "time_s": round(t2 - t1, 4), "iterations": it1,
+                               "rtol": 1e-8}
+        # one PCG iteration on a 12^3-hex sample of the N = 7 workload
+        ms, Ns = meshgen.cube_mesh(12, perturb=0.15, seed=1506, permute=True), N
+        t0 = time.perf_counter()
+        Ps = Problem(ms.vtx, ms.hex, Ns)
+        setup = time.perf_counter() - t0
+        bs = Ps.load(lambda x: meshgen.manufactured_s(x, ms.lengths))
+        t0 = time.perf_counter()
+        _, its, _, _ = Ps.solve(bs, rtol=1e-30, max_iter=3)
+        per_it = (time.perf_counter() - t0) / max(its, 1)
+        est = {"sample": f"12^3 hexes, N={Ns}, {Ps.num.n_global} DOFs, {its} iterations timed after a "
+                         f"{setup:.1f} s set-up", "s_per_iteration_sample": round(per_it, 3),
+               "s_per_iteration_scaled": round(per_it * mesh.n_elem / ms.n_elem, 1)}
+        if gpu_pcg_iterations:
+            est["gpu_fp64_iterations"] = gpu_pcg_iterations
+            est["time_s_estimated"] = round(per_it * mesh.n_elem / ms.n_elem * gpu_pcg_iterations, 1)
+        out["pcg_cube56_N7_estimate"] = est
+    out.update(host_info())
+    return out
 
 
 def run_batch(args):
+    """--workload batch64: the batch section alone, as its own JSON line."""
+    res, total, setup_s, inst = batch_section(args)
+    out = {"metric": "batched PCG time-to-1e-10, 64 instances (DOF/s, FP64)",
+           "value": round(total / res["fp64"]["time_s"], 1), "unit": "DOF/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "batch64", "instances": 64, "total_dofs": total, "setup_s": round(setup_s, 2),
+                      "orders": [d["N"] for d in inst], "k": [d["k"] for d in inst]},
+           "pcg": res}
+    print(json.dumps(out), flush=True)
+
+
+def batch_section(args):
     """64 independent solves of uneven size and order in one batched call
     (FP64 and FP32-refined, to a relative residual of 1e-10), against the same
     instances solved one after another through sem_pcg_solve."""
@@ -192,13 +279,151 @@ def run_batch(args):
         res["fp64_one_by_one_s"] = round(serial, 4)
         res["batch_speedup_fp64"] = round(serial / res["fp64"]["time_s"], 3)
         log(f"[bench] one by one fp64: {serial:.3f} s")
-    out = {"metric": "batched PCG time-to-1e-10, 64 instances (DOF/s, FP64)",
-           "value": round(total / res["fp64"]["time_s"], 1), "unit": "DOF/s", "n_gpus": 1,
-           "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "batch64", "instances": 64, "total_dofs": total, "setup_s": round(setup_s, 2),
-                      "orders": [d["N"] for d in inst], "k": [d["k"] for d in inst]},
-           "pcg": res}
-    print(json.dumps(out), flush=True)
+    B.close()
+    return res, total, setup_s, inst
+
+
+def run_stream(dev):
+    """Copy, triad and read bandwidth of the library's streaming probes over
+    three arrays of 2^28 doubles (2 GiB each)."""
+    from paper_1506_05996_amd import sem
+
+    r = sem.stream_bench(n=1 << 28, reps=10, device=dev.index or 0)
+    out = {k.replace("_gbs", "_tbs"): round(v / 1e3, 3) for k, v in r.items()}
+    out["arrays"] = "3 x 2^28 FP64"
+    log(f"[bench] stream: {out}")
+    return out
+
+
+def operator_rooflines(M, u, dt_bytes, steps, warmup, tiles):
+    """Per tile: element and gather kernel times (HIP events), GDOF/s and the
+    HBM fraction of the stored-factor algorithmic bytes at this precision."""
+    from paper_1506_05996_amd import sem
+
+    ng, nl = M.n_global, M.n_local
+    dtype = sem.SEM_F64 if dt_bytes == 8 else sem.SEM_F32
+    keep = M.tile(dtype)
+    y = u.new_empty(u.shape)
+    out = {}
+    for name, t in tiles:
+        M.set_tile(t, dtype)
+        for _ in range(warmup):
+            M.apply_A(u, y)
+        te, tg = M.time_apply_A(u, y, steps)
+        balg = algorithmic_bytes_ax(nl, ng, dt_bytes)
+        ach = balg / ((te + tg) * 1e-3) / 1e9
+        out[name] = {"ms_ax_kernel": round(te, 4), "ms_gs_kernel": round(tg, 4),
+                     "gdofs": round(ng / ((te + tg) * 1e-3) / 1e9, 2),
+                     "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(ach / HBM_PEAK_GBS, 4), "algorithmic_bytes": balg}}
+    M.set_tile(keep, dtype)
+    return out
+
+
+def solve_section(M, b, ue, mN, kw_common, reps, modes=(("fp64", 0), ("fp32_refined", 1))):
+    """PCG to the given tolerance in each mode: one warm-up, median of reps,
+    FP64 true residual, error against the exact solution (max and m-weighted
+    L2), refined against FP64."""
+    import numpy as np
+    import torch
+
+    res, x64 = {}, None
+    for name, mode in modes:
+        kw = dict(kw_common, mode=mode)
+        M.solve(b, **kw)
+        times = []
+        for _ in range(max(1, reps)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info = M.solve(b, **kw)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        r = b - M.apply_A(x)
+        err = x - ue
+        res[name] = {"time_s": round(float(np.median(times)), 4), "iterations": info["iterations"],
+                     "outer": info["outer"],
+                     "true_rel_residual": float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)),
+                     "err_max_vs_exact": float(err.abs().max()),
+                     "err_l2m_vs_exact": float(torch.sqrt((mN * err * err).sum())), "reps": len(times)}
+        if x64 is None:
+            x64 = x.clone()
+        else:
+            res[name]["rel_l2_vs_fp64"] = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+    if "fp64" in res and "fp32_refined" in res:
+        res["speedup_fp32_refined"] = round(res["fp64"]["time_s"] / res["fp32_refined"]["time_s"], 3)
+    return res
+
+
+def manufactured_rhs(M, lengths, dev):
+    import torch
+
+    import meshgen
+
+    m_n = M.lumped_mass()
+    x_n = M.node_coords()
+    mask = M.boundary_mask().astype(bool)
+    bh = m_n * meshgen.manufactured_s(x_n, lengths)
+    bh[mask] = 0.0
+    ue = meshgen.manufactured_u(x_n, lengths)
+    ue[mask] = 0.0
+    return (torch.tensor(bh, device=dev), torch.tensor(ue, device=dev), torch.tensor(m_n, device=dev))
+
+
+def run_order15(args, dev):
+    """20^3 hexahedra stretched 8:1 in z, N = 15: the operator with the FP64
+    and FP32 matrix-core kernels against the vector kernel, each against the
+    HBM roofline of its precision; PCG to 1e-10 in FP64 and FP32-refined form
+    (the autotuned tiles: matrix-core kernels in both)."""
+    import numpy as np
+    import torch
+
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    t0 = time.time()
+    mesh, N = meshgen.workload_mesh("box20x8_N15")
+    M = sem.Mesh(mesh.vtx, mesh.hex, N)
+    setup_s = time.time() - t0
+    log(f"[bench] box20x8_N15: n_global={M.n_global}, setup {setup_s:.1f} s, tiles {M.tile(0)} / {M.tile(1)}")
+    res = {"workload": "box20x8_N15", "hexes": mesh.n_elem, "order": N, "n_global": M.n_global,
+           "setup_s": round(setup_s, 2), "tile_fp64": M.tile(sem.SEM_F64), "tile_fp32": M.tile(sem.SEM_F32)}
+    u = torch.tensor(np.random.default_rng(1506).uniform(-1, 1, M.n_global), device=dev)
+    tiles = (("mfma", sem.TILE_MFMA), ("line_rebuilt", sem.TILE_LINE_GEO), ("line_stored", sem.TILE_LINE),
+             ("vector", 1))
+    res["ax_fp64"] = operator_rooflines(M, u, 8, 20, 3, tiles)
+    res["ax_fp32"] = operator_rooflines(M, u.float(), 4, 20, 3, tiles)
+    del u
+    log(f"[bench] box20x8_N15 Ax fp64 {res['ax_fp64']}")
+    log(f"[bench] box20x8_N15 Ax fp32 {res['ax_fp32']}")
+    b, ue, mN = manufactured_rhs(M, mesh.lengths, dev)
+    res["pcg"] = solve_section(M, b, ue, mN, dict(rtol=1e-10, max_iter=4000, inner_rtol=args.inner_rtol,
+                                                  max_outer=40), args.pcg_reps)
+    log(f"[bench] box20x8_N15 PCG {res['pcg']}")
+    M.close()
+    return res
+
+
+def run_small(args, dev):
+    """The 4^3-hex cube at N = 4: FP64 PCG to 1e-8 (latency), the refined form
+    to 1e-10 for inner tolerances 1e-2 .. 1e-5, and FP64 to 1e-10 beside it."""
+    import meshgen
+    from paper_1506_05996_amd import sem
+
+    mesh, N = meshgen.workload_mesh("cube4_N4")
+    M = sem.Mesh(mesh.vtx, mesh.hex, N)
+    b, ue, mN = manufactured_rhs(M, mesh.lengths, dev)
+    common = dict(max_iter=1000, max_outer=40)
+    res = {"workload": "cube4_N4", "n_global": M.n_global,
+           "fp64_rtol1e-8": solve_section(M, b, ue, mN, dict(common, rtol=1e-8), 5, (("fp64", 0),))["fp64"],
+           "fp64_rtol1e-10": solve_section(M, b, ue, mN, dict(common, rtol=1e-10), 5, (("fp64", 0),))["fp64"]}
+    sweep = {}
+    for it in (1e-2, 1e-3, 1e-4, 1e-5):
+        sweep[f"{it:g}"] = solve_section(M, b, ue, mN, dict(common, rtol=1e-10, inner_rtol=it), 5,
+                                         (("fp32_refined", sem.SOLVE_FP32_REFINED),))["fp32_refined"]
+    res["fp32_refined_inner_rtol"] = sweep
+    log(f"[bench] cube4_N4 {res}")
+    M.close()
+    return res
 
 
 def run_amg(M, b, dev, args):
@@ -420,6 +645,9 @@ def main():
     ap.add_argument("--no-amg", action="store_true", help="skip the PCG runs with the AMG coarse solver")
     ap.add_argument("--no-coef", action="store_true",
                     help="skip the per-element-coefficient / Neumann solve on the main mesh")
+    ap.add_argument("--no-n15", action="store_true", help="skip the N = 15 box section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch section")
+    ap.add_argument("--no-small", action="store_true", help="skip the 4^3, N = 4 cube section")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     ap.add_argument("--fine-precond", type=int, default=0, metavar="K",
@@ -458,6 +686,9 @@ def main():
         # n_global doubles (known bytes) that calibrates the counters
         for _ in range(3):
             M.apply_A(u, y)
+        u32, y32 = u.float(), y.float()
+        for _ in range(3):
+            M.apply_A(u32, y32)
         torch.cuda.synchronize()
         for _ in range(3):
             y.copy_(u)
@@ -473,6 +704,18 @@ def main():
         torch.cuda.synchronize()
         log(f"[bench] fine-preconditioner run done: {args.fine_precond} applications per dtype")
         return
+    # the device's streaming bandwidth and every operator kernel on this mesh
+    # (FP64 and FP32; the stored-factor ones against the HBM roofline of their
+    # algorithmic bytes), before the timed region
+    stream = run_stream(dev)
+    tiles = (("stored_plane", 1), ("stored_line", sem.TILE_LINE), ("rebuilt_plane", sem.TILE_GEO),
+             ("rebuilt_line", sem.TILE_LINE_GEO))
+    kernels = {"fp64": operator_rooflines(M, u, 8, args.steps, args.warmup, tiles),
+               "fp32": operator_rooflines(M, u.float(), 4, args.steps, args.warmup, tiles)}
+    for dt in ("fp64", "fp32"):
+        log(f"[bench] operator kernels {dt}: " + ", ".join(
+            f"{k} {v['ms_ax_kernel']:.3f}+{v['ms_gs_kernel']:.3f} ms ({v['gdofs']} GDOF/s)" for k, v in kernels[dt].items()))
+
     for _ in range(args.warmup):
         M.apply_A(u, y)
     torch.cuda.synchronize()
@@ -486,41 +729,37 @@ def main():
 
     balg = algorithmic_bytes_ax(nl, ng)
     tile = M.tile(sem.SEM_F64)
-    geo = tile == sem.TILE_GEO
+    geo = tile in (sem.TILE_GEO, sem.TILE_LINE_GEO)
+    kname = {sem.TILE_GEO: ("ax_kernel", "ax_kernel<7, double, 1, true, false>"),
+             sem.TILE_LINE_GEO: ("ax_line_kernel", "ax_line_kernel<7, double, 1, true, false>"),
+             sem.TILE_LINE: ("ax_line_kernel", "ax_line_kernel<7, double, 1, false, false>")}.get(
+        tile, ("ax_kernel", "ax_kernel<7, double, %d, false, false>" % tile))
     if geo:
         # the element kernel rebuilds the factors: arithmetic-bound, FP64 vector peak
         falg = algorithmic_flops_ax(nl, N, True)
         achieved = falg / (ms_elem * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
                     "frac": round(achieved / FP64_PEAK_TFS, 4),
-                    "traffic": traffic_from_counters("ax_kernel<7, double, 1, true, false>"),
-                    "kernel": "ax_kernel, factors rebuilt from the element vertices (tile %d)" % tile,
+                    "traffic": traffic_from_counters(kname[1]),
+                    "kernel": "%s, factors rebuilt from the element vertices (tile %d)" % (kname[0], tile),
                     "ms_ax_kernel": round(ms_elem, 4), "ms_gs_kernel": round(ms_gs, 4),
                     "algorithmic_flops": falg}
     else:
         achieved = balg / ((ms_elem + ms_gs) * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_from_counters("ax_kernel<7, double, %d, false, false>" % tile),
-                    "kernel": "sem_apply_A = ax_kernel (stored factors, tile %d) + gs_kernel" % tile,
+                    "traffic": traffic_from_counters(kname[1]),
+                    "kernel": "sem_apply_A = %s (stored factors, tile %d) + gs_kernel" % (kname[0], tile),
                     "ms_ax_kernel": round(ms_elem, 4), "ms_gs_kernel": round(ms_gs, 4),
                     "algorithmic_bytes": balg}
     # the whole application measured against the stored-factor HBM bound
     # (algorithmic bytes B_alg / time / 8 TB/s)
     roofline["frac_of_stored_factor_hbm_bound"] = round(balg / ((ms_elem + ms_gs) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-    if geo:
-        # the stored-factor kernel on the same mesh, for its HBM roofline
-        M.set_tile(1)
-        for _ in range(args.warmup):
-            M.apply_A(u, y)
-        se, sg = M.time_apply_A(u, y, args.steps)
-        M.set_tile(tile)
-        ach = balg / ((se + sg) * 1e-3) / 1e9
-        roofline["stored_factor_kernel"] = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                                            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                                            "ms_ax_kernel": round(se, 4), "ms_gs_kernel": round(sg, 4),
-                                            "algorithmic_bytes": balg}
-        log(f"[bench] stored-factor kernel: {se:.3f} + {sg:.3f} ms, {ach / HBM_PEAK_GBS:.3f} of HBM peak")
+    st = min((kernels["fp64"][k] for k in ("stored_plane", "stored_line")), key=lambda r: r["ms_ax_kernel"])
+    roofline["stored_factor_kernel"] = dict(st["roofline"], ms_ax_kernel=st["ms_ax_kernel"],
+                                            ms_gs_kernel=st["ms_gs_kernel"])
+    roofline["frac_of_stored_factor_bound_at_copy_rate"] = round(
+        balg / ((ms_elem + ms_gs) * 1e-3) / 1e12 / stream["copy_tbs"], 4)
 
     pcg = None
     if not args.no_pcg:
@@ -573,14 +812,23 @@ def main():
         coefs["per_node"] = run_node_coefficients(M, mesh, dev, args)
 
     heat = None
+    del u, y
     if not args.no_heat:
-        del u, y
         heat = run_heat(args, dev)
+
+    order15 = None if args.no_n15 else run_order15(args, dev)
+    batch = None
+    if not args.no_batch:
+        bres, btotal, bsetup, binst = batch_section(args)
+        batch = {"workload": "batch64", "instances": len(binst), "total_dofs": btotal, "setup_s": round(bsetup, 2),
+                 "orders": [d["N"] for d in binst], "k": [d["k"] for d in binst],
+                 "dofs_per_s_fp64": round(btotal / bres["fp64"]["time_s"], 1), "pcg": bres}
+    small = None if args.no_small else run_small(args, dev)
 
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU baseline (oracle) ...")
-        cpu = cpu_baseline(mesh, N, ng)
+        cpu = cpu_baseline(mesh, N, ng, gpu_pcg_iterations=pcg["fp64"]["iterations"] if pcg else None)
         log(f"[bench] CPU baseline: {cpu}")
 
     out = {"metric": METRIC, "value": round(value, 3), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
@@ -589,7 +837,9 @@ def main():
            "config": {"workload": args.workload, "hexes": mesh.n_elem, "order": N, "n_global": ng,
                       "perturbation": mesh.meta.get("perturb"), "seed": 1506, "step": "one FP64 apply of A",
                       "setup_s": round(setup_s, 2)},
-           "roofline": roofline, "pcg": pcg, "coefficients": coefs, "heat": heat, "cpu_baseline": cpu}
+           "roofline": roofline, "stream_copy_tbs": stream["copy_tbs"], "stream": stream,
+           "operator_kernels": kernels, "pcg": pcg, "coefficients": coefs, "heat": heat,
+           "box20x8_N15": order15, "batch64": batch, "cube4_N4": small, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 

@@ -364,6 +364,20 @@ int sem_batch_destroy(sem_batch b);
 int sem_time_apply_A(sem_mesh m, const void* u_dev, void* y_dev, int dtype, int reps, void* stream,
                      double* ms_element, double* ms_gather);
 
+/*
+ * sem_stream_bench -- the device's achievable memory bandwidth with the
+ * library's own streaming kernels, the ceiling against which the solver's
+ * bandwidth-bound kernels are read (the paper's Section 6.1 reads its kernels
+ * against the device bandwidth the same way).  a, b, c: caller-owned device
+ * FP64 arrays of n entries each (n even, 16-byte aligned, no overlap); b and
+ * c are overwritten.  Runs b = a (copy, 16 n bytes), c = a + 0.5 b (triad,
+ * 24 n bytes) and a read-only sum of a (8 n bytes) on `stream`, reps timed
+ * launches each for several grid sizes, synchronises, and returns the best
+ * rate of each in gbs[0..2] (GB/s, 1e9 bytes).  SEM_EINVAL on bad arguments.
+ */
+int sem_stream_bench(const double* a_dev, double* b_dev, double* c_dev, int64_t n, int reps, void* stream,
+                     double* gbs);
+
 /* Tile of the operator kernel for dtype: elements per workgroup (1, 2, 4, 8;
    (N+1)^2 lanes each, at most 1024 lanes), 16 for the matrix-core kernel
    (N = 15 only, FP64 or FP32), or 32 for the kernel that rebuilds the geometric

@@ -1672,6 +1672,52 @@ int sem_time_apply_A(sem_mesh m, const void* u, void* y, int dtype, int reps, vo
   });
 }
 
+int sem_stream_bench(const double* a, double* b, double* c, int64_t n, int reps, void* stream, double* gbs) {
+  if (!a || !b || !c || !gbs || n < 2 || (n & 1) || reps < 1 || a == b || a == c || b == c ||
+      !aligned16(a, b, c))
+    return SEM_EINVAL;
+  return guarded([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n2 = n / 2;
+    hipEvent_t e0, e1;
+    SEM_HIP(hipEventCreate(&e0));
+    SEM_HIP(hipEventCreate(&e1));
+    struct Cleanup {
+      hipEvent_t a, b;
+      ~Cleanup() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+      }
+    } cleanup{e0, e1};
+    const double bytes[3] = {16.0 * n, 24.0 * n, 8.0 * n};
+    for (int q = 0; q < 3; ++q) gbs[q] = 0.0;
+    // best over grid sizes (workgroups of 256 lanes), each timed over reps launches
+    for (int grid : {1024, 2048, 4096, 8192, 16384}) {
+      const int g = (int)std::min<int64_t>(grid, (n2 + 255) / 256);
+      for (int q = 0; q < 3; ++q) {
+        auto launch = [&]() {
+          if (q == 0)
+            hipLaunchKernelGGL(stream_copy_kernel, dim3(g), dim3(256), 0, s, (double2*)b, (const double2*)a, n2);
+          else if (q == 1)
+            hipLaunchKernelGGL(stream_triad_kernel, dim3(g), dim3(256), 0, s, (double2*)c, (const double2*)a,
+                               (const double2*)b, 0.5, n2);
+          else  // the partial sums land in c (g <= n2 entries)
+            hipLaunchKernelGGL(stream_read_kernel, dim3(g), dim3(256), 0, s, (const double2*)a, n2, c);
+        };
+        launch();
+        SEM_HIP(hipEventRecord(e0, s));
+        for (int r = 0; r < reps; ++r) launch();
+        SEM_HIP(hipEventRecord(e1, s));
+        SEM_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        SEM_HIP(hipEventElapsedTime(&ms, e0, e1));
+        gbs[q] = std::max(gbs[q], bytes[q] * reps / (ms * 1e-3) / 1e9);
+      }
+    }
+    return SEM_OK;
+  });
+}
+
 int sem_precond(sem_mesh m, const void* r, void* z, int dtype, int pc, void* stream) {
   int st = need_device(m);
   if (st) return st;

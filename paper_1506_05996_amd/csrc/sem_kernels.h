@@ -1619,6 +1619,35 @@ __global__ void __launch_bounds__(256) copy_kernel(TD* __restrict__ d, const TS*
     d[q] = (TD)s[q];
 }
 
+// Bandwidth probes (copy, triad, read) over n doubles as double2 pairs with a
+// grid-stride loop: the on-device ceiling that the streaming kernels of the
+// solver are compared with.  n is even and the pointers are 16-byte aligned.
+__global__ void __launch_bounds__(256) stream_copy_kernel(double2* __restrict__ b, const double2* __restrict__ a,
+                                                          int64_t n2) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2; q += (int64_t)gridDim.x * blockDim.x)
+    b[q] = a[q];
+}
+
+__global__ void __launch_bounds__(256) stream_triad_kernel(double2* __restrict__ c, const double2* __restrict__ a,
+                                                           const double2* __restrict__ b, double s, int64_t n2) {
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2; q += (int64_t)gridDim.x * blockDim.x) {
+    const double2 x = a[q], y = b[q];
+    c[q] = make_double2(x.x + s * y.x, x.y + s * y.y);
+  }
+}
+
+__global__ void __launch_bounds__(256) stream_read_kernel(const double2* __restrict__ a, int64_t n2,
+                                                          double* __restrict__ part) {
+  double v = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n2; q += (int64_t)gridDim.x * blockDim.x) {
+    const double2 x = a[q];
+    v += x.x + x.y;
+  }
+  __shared__ double red[4];
+  const double t = group_sum<256>(v, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 // Right-hand side of one backward Euler step of the heat equation (Section
 // 6.2): b_N = m_N (u_N / dt + q_N) on free nodes, 0 on Dirichlet nodes
 // (q = NULL: no source).

@@ -38,7 +38,7 @@ EXPORTS = [
     "sem_time_apply_A", "sem_mesh_tile", "sem_mesh_set_tile", "sem_mesh_coarse_factor_size", "sem_last_error", "sem_batch_setup", "sem_batch_sizes", "sem_batch_solve",
     "sem_batch_destroy", "sem_mesh_set_coefficients", "sem_mesh_coefficients", "sem_heat_step",
     "sem_mesh_set_element_coefficients", "sem_mesh_set_node_coefficients", "sem_mesh_boundary_face_mass", "sem_mesh_set_coarse_solver",
-    "sem_mesh_amg_hierarchy", "sem_pcg_solve_noalloc",
+    "sem_mesh_amg_hierarchy", "sem_pcg_solve_noalloc", "sem_stream_bench",
 ]
 
 
@@ -78,6 +78,7 @@ _lib.sem_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, _p]
 _lib.sem_precond.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p]
 _lib.sem_coarse_solve.argtypes = [_p, _p, _p, _p]
 _lib.sem_pcg_solve.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
+_lib.sem_stream_bench.argtypes = [_p, _p, _p, ctypes.c_int64, ctypes.c_int, _p, ctypes.POINTER(ctypes.c_double)]
 _lib.sem_pcg_solve_noalloc.argtypes = [_p, _p, _p, ctypes.POINTER(SolveOpts), ctypes.POINTER(SolveStats), _p]
 _lib.sem_time_apply_A.argtypes = [_p, _p, _p, ctypes.c_int, ctypes.c_int, _p, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
@@ -507,6 +508,18 @@ class Batch:
         if status != SEM_OK and (status != SEM_ENOCONV or raise_on_noconv):
             raise SemError(status, last_error())
         return xs, infos, status
+
+
+def stream_bench(n=1 << 28, reps=10, device=0):
+    """Copy, triad and read bandwidth (GB/s) of the library's streaming probes
+    over three fresh FP64 arrays of n entries on `device`."""
+    import torch
+    dev = torch.device("cuda", device)
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b, c = torch.empty_like(a), torch.empty_like(a)
+    out = (ctypes.c_double * 3)()
+    _check(_lib.sem_stream_bench(_dptr(a), _dptr(b), _dptr(c), int(n), int(reps), _stream(None), out))
+    return {"copy_gbs": out[0], "triad_gbs": out[1], "read_gbs": out[2]}
 
 
 def library_symbols():
