@@ -648,6 +648,8 @@ def main():
     ap.add_argument("--no-n15", action="store_true", help="skip the N = 15 box section")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-instance batch section")
     ap.add_argument("--no-small", action="store_true", help="skip the 4^3, N = 4 cube section")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="counters/profiling runs: force this operator tile in both precisions (0: autotuned)")
     ap.add_argument("--counters", action="store_true",
                     help="counter-collection run: 3 FP64 applies and 3 copies of a vector of known size, no timing")
     ap.add_argument("--fine-precond", type=int, default=0, metavar="K",
@@ -684,6 +686,10 @@ def main():
     if args.counters:
         # rocprofv3 --pmc runs: the operator, then a plain device copy of
         # n_global doubles (known bytes) that calibrates the counters
+        if args.tile:
+            M.set_tile(args.tile, sem.SEM_F64)
+            M.set_tile(args.tile, sem.SEM_F32)
+        log(f"[bench] counters run: tiles {M.tile(sem.SEM_F64)} / {M.tile(sem.SEM_F32)}")
         for _ in range(3):
             M.apply_A(u, y)
         u32, y32 = u.float(), y.float()

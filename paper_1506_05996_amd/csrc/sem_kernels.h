@@ -1049,13 +1049,13 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
   // the three records of the lane's k-pencil, then all its residual values
   const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
   const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
-  T rv[n1];
+  T rv[n1];  // loaded only where the element owns the node (each global node once)
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
     const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
     int ai, aj, ak;
     unpack_coef(rr.y, ai, aj, ak);
-    rv[k] = r[rr.x + ai * i + aj * j + ak * k];
+    rv[k] = (rr.w & kFlagOwned) ? r[rr.x + ai * i + aj * j + ak * k] : T(0);
   }
   __syncthreads();
   double acc[8];
