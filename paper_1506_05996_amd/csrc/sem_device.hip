@@ -562,7 +562,8 @@ void ensure_side_stream(sem_mesh m) {
 }
 
 template <typename T>
-void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s);
+void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s,
+                 bool coarse_started = false);
 
 template <typename T>
 void precond(sem_mesh m, const T* r, T* z, int pc, hipStream_t s) {
@@ -574,8 +575,12 @@ void dot(sem_mesh m, const TA* a, const TB* b, int dst, int mode, hipStream_t s)
 
 // z = P r; with dot_dst >= 0 also r . z into scalar slot dot_dst (dot_final
 // mode dot_mode), taken from the preconditioner's own output kernels
+// coarse_started: the coarse chain of this application (restriction, coarse
+// solve) is already running on the side stream (pcg_core forks it right after
+// the update of r); only its join remains.
 template <typename T>
-void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s) {
+void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode, hipStream_t s,
+                 bool coarse_started) {
   const HostTables& H = m->T;
   const bool fine = pc & SEM_PC_FINE, coarse = (pc & SEM_PC_COARSE) && H.nc > 0;
   if (pc == SEM_PC_NONE) {
@@ -590,12 +595,18 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
   // The patch solves are issued first, so that the host's launches of the
   // coarse chain do not hold them back.
   hipStream_t sc = s;
-  if (coarse && fine) {
+  if (coarse_started) {
+    fdm_and_restrict<T>(m, r, true, false, s);
+    SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
+  } else if (coarse && fine) {
     ensure_side_stream(m);
     SEM_HIP(hipEventRecord(m->ev_fork, s));
     SEM_HIP(hipStreamWaitEvent(m->side_stream, m->ev_fork, 0));
     sc = m->side_stream;
   }
+  if (coarse_started) {
+    // fine part and join done above
+  } else {
   if (fine) fdm_and_restrict<T>(m, r, true, false, s);
   if (coarse) {
     fdm_and_restrict<T>(m, r, false, true, sc);
@@ -608,6 +619,7 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
     SEM_HIP(hipEventRecord(m->ev_join, sc));
     SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
   }
+  }
   if (dot_dst < 0) {
     schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s);
     return;
@@ -619,6 +631,51 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
                      chunk);
   hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dot_dst, dot_mode);
   SEM_HIP(hipGetLastError());
+}
+
+// PCG's update of r fused with the coarse restriction (update_r_restrict_kernel),
+// r . r into scalar slot 4, then the rest of the coarse chain (vertex sums,
+// coarse solve) forked onto the side stream; precond_dot(..., true) joins it.
+template <int N, typename T>
+int64_t launch_update_r_restrict(sem_mesh m, T* r, const T* w, hipStream_t s) {
+  const int64_t grid = xcd_grid(m->T.E);
+  hipLaunchKernelGGL((update_r_restrict_kernel<N, T>), dim3((unsigned)grid), dim3((N + 1) * (N + 1)), 0, s, r, w,
+                     (const double*)m->wk.sc, m->Re.p, m->wk.dpart, m->rec.p, (const double*)m->phi.p, m->order.p,
+                     m->T.E);
+  SEM_HIP(hipGetLastError());
+  return grid;
+}
+
+template <typename T>
+void update_r_and_fork_coarse(sem_mesh m, T* r, const T* w, hipStream_t s) {
+  int64_t n = 0;
+  switch (m->T.N) {
+#define CASE(NN)                                             \
+  case NN:                                                   \
+    n = launch_update_r_restrict<NN, T>(m, r, w, s);         \
+    break;
+    CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8) CASE(9) CASE(10) CASE(11) CASE(12) CASE(13) CASE(14)
+    CASE(15)
+#undef CASE
+    default:
+      throw Error{SEM_EUNSUPPORTED, "order not compiled"};
+  }
+  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+  const int nb = (int)((n + chunk - 1) / chunk);
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
+                     chunk);
+  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, 4, 0);
+  SEM_HIP(hipGetLastError());
+  const HostTables& H = m->T;
+  ensure_side_stream(m);
+  hipStream_t sc = m->side_stream;
+  SEM_HIP(hipEventRecord(m->ev_fork, s));
+  SEM_HIP(hipStreamWaitEvent(sc, m->ev_fork, 0));
+  hipLaunchKernelGGL(restrict_gather_kernel, dim3((unsigned)blocks_for(H.V)), dim3(kGS), 0, sc, m->Rlev.p, m->Re.p,
+                     m->vinc_off.p, m->vinc_ec.p, m->cidx.p, H.V);
+  SEM_HIP(hipGetLastError());
+  coarse_solve_tree(m, sc);
+  SEM_HIP(hipEventRecord(m->ev_join, sc));
 }
 
 // --- coarse factorisation (set-up), multifrontal in post-order.  Node t's
@@ -978,12 +1035,21 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int
   hipLaunchKernelGGL((copy_kernel<T, T>), dim3(gb), dim3(kGS), 0, s, p, z, n);
   int status = SEM_ENOCONV;
   bool pending_x = false;  // x += alpha p of the last iteration not yet applied
+  // two-scale P with a coarse space: the update of r also restricts it, and
+  // the coarse solve starts beside the convergence check and the patch solves
+  const bool fused = pc == SEM_PC_TWOSCALE && m->T.nc > 0 && !m->direct_coarse;
+  bool coarse_pending = false;
   while (k < max_iter) {
     apply_A_dot<T>(m, p, w, 1, 1, s);
-    hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)sc,
-                       m->wk.part, n, (int)aligned16(r, w));
-    SEM_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, sc, nb, 4, 0);
+    if (fused) {
+      update_r_and_fork_coarse<T>(m, r, (const T*)w, s);
+      coarse_pending = true;
+    } else {
+      hipLaunchKernelGGL((update_r_kernel<T>), dim3(nb), dim3(kRedThreads), 0, s, r, (const T*)w, (const double*)sc,
+                         m->wk.part, n, (int)aligned16(r, w));
+      SEM_HIP(hipGetLastError());
+      hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, sc, nb, 4, 0);
+    }
     ++k;
     pending_x = true;
     if (k % check_every == 0 || k == max_iter) {
@@ -1004,12 +1070,16 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int
         break;
       }
     }
-    precond_dot<T>(m, r, z, pc, 5, 2, s);
+    precond_dot<T>(m, r, z, pc, 5, 2, s, coarse_pending);
+    coarse_pending = false;
     hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)sc, n,
                        (int)aligned16(x, p, z));
     SEM_HIP(hipGetLastError());
     pending_x = false;
   }
+  // a coarse solve forked for an iteration that did not follow: the caller's
+  // stream waits for it, so no later work on the handle overlaps it
+  if (coarse_pending) SEM_HIP(hipStreamWaitEvent(s, m->ev_join, 0));
   if (pending_x && status != SEM_EBREAKDOWN) {
     hipLaunchKernelGGL((update_x_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, (const T*)p, (const double*)sc, n);
     SEM_HIP(hipGetLastError());

@@ -1089,6 +1089,79 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
   }
 }
 
+// r -= alpha w at the nodes each element owns (each global node once), with
+// the element's part of the coarse restriction of the updated r (as
+// restrict_kernel: Re[e][IJK] = sum over the owned nodes of
+// Phi_I(t_i) Phi_J(t_j) Phi_K(t_k) r_N) and of r . r (dpart[block], 0 for
+// the padding blocks).  Lets the coarse chain start right after the update
+// of r, before the patch solves.
+template <int N, typename T>
+__global__ void __launch_bounds__((N + 1) * (N + 1))
+update_r_restrict_kernel(T* __restrict__ r, const T* __restrict__ w, const double* __restrict__ sc,
+                         double* __restrict__ Re, double* __restrict__ dpart, const int32_t* __restrict__ rec,
+                         const double* __restrict__ phi, const int32_t* __restrict__ order, int64_t E) {
+  constexpr int n1 = N + 1, P = n1 * n1;
+  __shared__ double red[9][P + 1];  // padded rows: the summing lanes read distinct banks
+  __shared__ double sPhi[2 * n1];
+  const int tid = threadIdx.x;
+  const int i = tid % n1, j = tid / n1;
+  const int64_t pos = xcd_position(blockIdx.x, E);
+  const bool valid = pos < E;
+  const int64_t e = valid ? order[pos] : 0;
+  for (int x = tid; x < 2 * n1; x += P) sPhi[x] = phi[x];
+  const int cx = node_class(i, N), cy = node_class(j, N);
+  const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
+  const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
+  const T al = (T)sc[2];
+  T rv[n1], wv[n1];
+  int64_t gk[n1];
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
+    int ai, aj, ak;
+    unpack_coef(rr.y, ai, aj, ak);
+    const bool own = valid && (rr.w & kFlagOwned);
+    gk[k] = own ? rr.x + ai * i + aj * j + ak * k : -1;
+    rv[k] = own ? r[gk[k]] : T(0);
+    wv[k] = own ? w[gk[k]] : T(0);
+  }
+  __syncthreads();
+  double acc[8], rsq = 0.0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+#pragma unroll
+  for (int k = 0; k < n1; ++k) {
+    if (gk[k] < 0) continue;
+    const T rn = rv[k] - al * wv[k];
+    r[gk[k]] = rn;
+    const double v = (double)rn;
+    rsq += v * v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      acc[c] += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * v;
+  }
+#pragma unroll
+  for (int c = 0; c < 8; ++c) red[c][tid] = acc[c];
+  red[8][tid] = rsq;
+  __syncthreads();
+  if (tid < 9) {
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int x = 0;
+    for (; x + 3 < P; x += 4) {
+      s0 += red[tid][x];
+      s1 += red[tid][x + 1];
+      s2 += red[tid][x + 2];
+      s3 += red[tid][x + 3];
+    }
+    for (; x < P; ++x) s0 += red[tid][x];
+    const double t = (s0 + s1) + (s2 + s3);
+    if (tid == 8)
+      dpart[blockIdx.x] = t;
+    else if (valid)
+      Re[e * 8 + tid] = t;
+  }
+}
+
 // coarse residual on the free vertices (coarse order): sum of the element parts
 __global__ void __launch_bounds__(256)
 restrict_gather_kernel(double* __restrict__ R, const double* __restrict__ Re, const int32_t* __restrict__ vinc_off,
