@@ -468,7 +468,12 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
 #pragma unroll 1
   for (int k = 0; k < n1; ++k) {
     const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
-    T g0, g1, g2, g3, g4, g5;
+    const int o = k * PS + b * LS + a;
+    const T ur = X[o], us = Z[o];
+    T ut = 0;
+#pragma unroll
+    for (int m = 0; m < n1; ++m) ut += Dk[m] * uv[m];
+    T A, B, C;
     if constexpr (GEO) {
       const T tk = tq[k];
       const T f0k = T(0.5) * (T(1) - tk), f1k = T(0.5) * (T(1) + tk);
@@ -483,30 +488,20 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
       const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
       const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
       T sc = rij * tq[n1 + k] * recip_pos(det);
-      if constexpr (KN) sc *= pick(kv, k);
-      g0 = sc * (a0x * a0x + a0y * a0y + a0z * a0z);
-      g1 = sc * (a0x * a1x + a0y * a1y + a0z * a1z);
-      g2 = sc * (a0x * a2x + a0y * a2y + a0z * a2z);
-      g3 = sc * (a1x * a1x + a1y * a1y + a1z * a1z);
-      g4 = sc * (a1x * a2x + a1y * a2y + a1z * a2z);
-      g5 = sc * (a2x * a2x + a2y * a2y + a2z * a2z);
+      if constexpr (KN) sc *= pick(kv, k);  // kappa at the node (eq. (R))
+      // G = sc M M^T (M: rows a0, a1, a2): (A, B, C) = sc M (M^T grad u)
+      const T vx = ur * a0x + us * a1x + ut * a2x, vy = ur * a0y + us * a1y + ut * a2y,
+              vz = ur * a0z + us * a1z + ut * a2z;
+      A = sc * (a0x * vx + a0y * vy + a0z * vz);
+      B = sc * (a1x * vx + a1y * vy + a1z * vz);
+      C = sc * (a2x * vx + a2y * vy + a2z * vz);
     } else {
       const T* Gk = Ge + k * P;
-      g0 = Gk[0 * NN];
-      g1 = Gk[1 * NN];
-      g2 = Gk[2 * NN];
-      g3 = Gk[3 * NN];
-      g4 = Gk[4 * NN];
-      g5 = Gk[5 * NN];
+      const T g0 = Gk[0 * NN], g1 = Gk[1 * NN], g2 = Gk[2 * NN], g3 = Gk[3 * NN], g4 = Gk[4 * NN], g5 = Gk[5 * NN];
+      A = g0 * ur + g1 * us + g2 * ut;
+      B = g1 * ur + g3 * us + g4 * ut;
+      C = g2 * ur + g4 * us + g5 * ut;
     }
-    const int o = k * PS + b * LS + a;
-    const T ur = X[o], us = Z[o];
-    T ut = 0;
-#pragma unroll
-    for (int m = 0; m < n1; ++m) ut += Dk[m] * uv[m];
-    const T A = g0 * ur + g1 * us + g2 * ut;
-    const T B = g1 * ur + g3 * us + g4 * ut;
-    const T C = g2 * ur + g4 * us + g5 * ut;
     X[o] = A;
     Z[o] = B;
 #pragma unroll

@@ -355,3 +355,22 @@ def test_noalloc_solve_rejects_meshes_beyond_its_scratch():
     assert fn(M.handle, b, x, ctypes.byref(o32), ctypes.byref(st), None) == sem.SEM_EINVAL
     msg = sem.last_error()
     assert "static scratch" in msg and str(128 << 20) in msg
+
+
+def test_stream_bench_rejects_bad_arguments_before_any_device_call():
+    """sem_stream_bench validates its arguments on the host: NULL or aliased
+    arrays, an odd or too small length, unaligned pointers and reps < 1 give
+    SEM_EINVAL without touching the device."""
+    lib = ctypes.CDLL(sem.LIB_PATH)
+    fn = lib.sem_stream_bench
+    fn.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.POINTER(ctypes.c_double)]
+    out = (ctypes.c_double * 3)()
+    a, b, c = ctypes.c_void_p(4096), ctypes.c_void_p(8192), ctypes.c_void_p(12288)
+    assert fn(None, b, c, 16, 1, None, out) == sem.SEM_EINVAL
+    assert fn(a, a, c, 16, 1, None, out) == sem.SEM_EINVAL
+    assert fn(a, b, c, 15, 1, None, out) == sem.SEM_EINVAL
+    assert fn(a, b, c, 0, 1, None, out) == sem.SEM_EINVAL
+    assert fn(a, b, c, 16, 0, None, out) == sem.SEM_EINVAL
+    assert fn(ctypes.c_void_p(4104), b, c, 16, 1, None, out) == sem.SEM_EINVAL
+    assert fn(a, b, c, 16, 1, None, None) == sem.SEM_EINVAL
