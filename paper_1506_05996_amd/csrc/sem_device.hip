@@ -305,7 +305,7 @@ template <int N, typename T>
 void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
   T* zc = ZOp<T>(m);
   T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
-  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid(m->T.E)), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
+  hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid((m->T.E + fdm_ppb<N>() - 1) / fdm_ppb<N>())), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
                      m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E,
                      (T)m->T.kappa, (T)m->T.cmass, m->per_elem ? KEp<T>(m) : nullptr,
                      m->per_elem ? CEp<T>(m) : nullptr);

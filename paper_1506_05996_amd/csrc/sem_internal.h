@@ -83,7 +83,7 @@ struct HostTables {
 
   // reference data
   std::vector<double> t, rho, D;  // D[i*(N+1)+j] = phi_j'(t_i)
-  std::vector<double> S, lam;     // fast-diagonalisation basis [(N+3)^2], eigenvalues [N+3]
+  std::vector<double> S, lam;     // fast-diagonalisation basis by parity (packed, [(N+3)/2 rows][N+3] + middle row), eigenvalues [N+3]
 
   // numbering and gather
   std::vector<int32_t> rec;              // [E][27][4]

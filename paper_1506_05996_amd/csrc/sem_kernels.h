@@ -767,84 +767,121 @@ gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict_
 // correction at the element's own nodes goes to zc; the slots outside the
 // element go to the consumer layout of the element that holds them (zx).
 // ---------------------------------------------------------------------------
+// Patches per workgroup: each patch has m^2 pencils (m = N + 3), one per
+// lane in each pass; several patches share a workgroup so that the lanes in use
+// come close to a multiple of 64 (N = 7: 5 x 100 of 512), within ~64 KB of LDS
+// in FP64.
 template <int N>
-constexpr int fdm_threads() {
-  return (((N + 3) * (N + 3) + 63) / 64) * 64;
+constexpr int fdm_ppb() {
+  return N == 2 ? 5 : N == 3 ? 7 : N == 4 ? 5 : N == 6 ? 3 : N == 7 ? 5 : N == 9 ? 3 : N == 10 ? 3 : N == 11 ? 2 : 1;
 }
 
-// one 1D pass of the fast diagonalisation on a lane's pencil, S (m x m,
-// row-major, in global memory) read a row at a time with wave-uniform
-// addresses (scalar loads feeding the FMAs directly).  The outer loop stays
-// rolled so that S is not hoisted into registers.
-//   pencil_St: out[b] = sum_a S[a][b] x[a stride]     (x in LDS)
-//   pencil_S:  y[a stride] = scale sum_b S[a][b] v[b]  (y in LDS)
+template <int N>
+constexpr int fdm_threads() {
+  return ((fdm_ppb<N>() * (N + 3) * (N + 3) + 63) / 64) * 64;
+}
+
+// One 1D pass of the fast diagonalisation on a lane's pencil.  The extended
+// pencil is symmetric under a -> m-1-a, so every column of S is even or odd:
+// with ho = m/2 pairs (a, m-1-a) and he = m - ho even columns, the pencil's
+// transform takes the pair sums x_a + x_{m-1-a} against the even columns and
+// the differences against the odd ones (about half the products of a full
+// m x m pass).  Transformed coefficients sit in the order (even columns
+// ascending, odd columns ascending).  Sp holds, for a < ho, row a as
+// S[a][even j] (j < he) then S[a][odd j] (j < ho), and for odd m the middle
+// row S[ho][even j]; rows are read with wave-uniform addresses (scalar loads
+// feeding the FMAs) in a rolled loop, so S is not hoisted into registers.
+//   pencil_St: out = S^T x     (x in LDS, stride apart)
+//   pencil_S:  y = scale S v    (y in LDS)
 template <int m, typename T>
-__device__ __forceinline__ void pencil_St(const T* __restrict__ sS, const T* x, int stride, T (&out)[m]) {
+__device__ __forceinline__ void pencil_St(const T* __restrict__ Sp, const T* x, int stride, T (&out)[m]) {
+  constexpr int ho = m / 2, he = m - ho;
 #pragma unroll
   for (int b = 0; b < m; ++b) out[b] = T(0);
 #pragma unroll 1
-  for (int a = 0; a < m; ++a) {
-    const T va = x[a * stride];
-    const T* sr = sS + a * m;
+  for (int a = 0; a < ho; ++a) {
+    const T xl = x[a * stride], xr = x[(m - 1 - a) * stride];
+    const T ps = xl + xr, ms = xl - xr;
+    const T* sr = Sp + a * m;
 #pragma unroll
-    for (int b = 0; b < m; ++b) out[b] += sr[b] * va;
+    for (int j = 0; j < he; ++j) out[j] += sr[j] * ps;
+#pragma unroll
+    for (int j = 0; j < ho; ++j) out[he + j] += sr[he + j] * ms;
+  }
+  if constexpr (m % 2 == 1) {
+    const T xc = x[ho * stride];
+    const T* sr = Sp + ho * m;
+#pragma unroll
+    for (int j = 0; j < he; ++j) out[j] += sr[j] * xc;
   }
 }
 
 template <int m, typename T>
-__device__ __forceinline__ void pencil_S(const T* __restrict__ sS, const T (&v)[m], T* y, int stride, T scale) {
+__device__ __forceinline__ void pencil_S(const T* __restrict__ Sp, const T (&v)[m], T* y, int stride, T scale) {
+  constexpr int ho = m / 2, he = m - ho;
 #pragma unroll 1
-  for (int a = 0; a < m; ++a) {
-    const T* sr = sS + a * m;
-    T acc = T(0);
+  for (int a = 0; a < ho; ++a) {
+    const T* sr = Sp + a * m;
+    T ev = T(0), od = T(0);
 #pragma unroll
-    for (int b = 0; b < m; ++b) acc += sr[b] * v[b];
-    y[a * stride] = acc * scale;
+    for (int j = 0; j < he; ++j) ev += sr[j] * v[j];
+#pragma unroll
+    for (int j = 0; j < ho; ++j) od += sr[he + j] * v[he + j];
+    y[a * stride] = (ev + od) * scale;
+    y[(m - 1 - a) * stride] = (ev - od) * scale;
+  }
+  if constexpr (m % 2 == 1) {
+    const T* sr = Sp + ho * m;
+    T ev = T(0);
+#pragma unroll
+    for (int j = 0; j < he; ++j) ev += sr[j] * v[j];
+    y[ho * stride] = ev * scale;
   }
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 9 ? 4 : 2, 8)))
+__global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 8 ? 8 : 4, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
            const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
            const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E,
            T kap, T cm, const T* __restrict__ ke, const T* __restrict__ ce) {
-  constexpr int m = N + 3, MM = m * m, MMM = MM * m, NT = fdm_threads<N>();
-  __shared__ T X[MMM];
+  constexpr int m = N + 3, MM = m * m, MMM = MM * m, PPB = fdm_ppb<N>(), NT = fdm_threads<N>();
+  constexpr int NN = (N + 1) * (N + 1) * (N + 1), NX = MMM - NN, R = (PPB * MMM + NT - 1) / NT;
+  __shared__ T X[PPB * MMM];
   __shared__ T sL[m];
+  __shared__ int64_t sE[PPB];  // element of each patch slot, -1 past the end
   const int tid = threadIdx.x;
-  const int64_t pos = xcd_position(blockIdx.x, E);
-  if (pos >= E) return;  // whole workgroup
-  const int64_t e = order[pos];
-  const int32_t* ipe = ip + e * MMM;
+  const int64_t pos0 = xcd_position(blockIdx.x, (E + PPB - 1) / PPB) * PPB;
+  if (pos0 >= E) return;  // whole workgroup
+  if (tid < PPB) sE[tid] = pos0 + tid < E ? (int64_t)order[pos0 + tid] : -1;
+  if (tid < m) sL[tid] = lam[tid];
+  __syncthreads();
   {
     // all index loads, then all residual loads, then the LDS stores
-    constexpr int R = (MMM + NT - 1) / NT;
     int32_t gi[R];
 #pragma unroll
-    for (int q = 0; q < R; ++q) gi[q] = (tid + q * NT < MMM) ? ipe[tid + q * NT] : -1;
+    for (int q = 0; q < R; ++q) {
+      const int x = tid + q * NT, lp = min(x / MMM, PPB - 1);
+      const int64_t e = x < PPB * MMM ? sE[lp] : -1;
+      gi[q] = e >= 0 ? ip[e * MMM + (x - lp * MMM)] : -1;
+    }
     T rv[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) rv[q] = r[gi[q] >= 0 ? gi[q] : 0];
-    if (tid < m) sL[tid] = lam[tid];
 #pragma unroll
     for (int q = 0; q < R; ++q)
-      if (tid + q * NT < MMM) X[tid + q * NT] = gi[q] >= 0 ? rv[q] : T(0);
+      if (tid + q * NT < PPB * MMM) X[tid + q * NT] = gi[q] >= 0 ? rv[q] : T(0);
   }
   __syncthreads();
-  const T hx = hg[e * 3 + 0], hy = hg[e * 3 + 1], hz = hg[e * 3 + 2];
-  const T ihx2 = T(4) / (hx * hx), ihy2 = T(4) / (hy * hy), ihz2 = T(4) / (hz * hz);
-  const T vscale = T(8) / (hx * hy * hz);
-  if (ke != nullptr) {  // the subdomain's own element's coefficients
-    kap = ke[e];
-    cm = ce[e];
-  }
-  const bool act = tid < MM;
-  const int p0 = tid % m, p1 = tid / m;
+  const bool act = tid < PPB * MM;
+  const int lp = act ? tid / MM : 0, pl = tid - lp * MM;
+  const int p0 = pl % m, p1 = pl / m;
+  const int64_t e = act && sE[lp] >= 0 ? sE[lp] : 0;  // slots past the end run on zeros
+  T* Xp = X + lp * MMM;
   T v[m], o[m];
   // pass 1: xi, S^T   (lane owns row (b = p0, c = p1))
   if (act) {
-    T* row = X + p1 * MM + p0 * m;
+    T* row = Xp + p1 * MM + p0 * m;
     pencil_St<m, T>(S, row, 1, o);
 #pragma unroll
     for (int a = 0; a < m; ++a) row[a] = o[a];
@@ -852,7 +889,7 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   __syncthreads();
   // pass 2: eta, S^T  (lane owns column (a = p0, c = p1))
   if (act) {
-    T* col = X + p1 * MM + p0;
+    T* col = Xp + p1 * MM + p0;
     pencil_St<m, T>(S, col, m, o);
 #pragma unroll
     for (int b = 0; b < m; ++b) col[b * m] = o[b];
@@ -860,17 +897,24 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   __syncthreads();
   // pass 3: zeta, S^T, diagonal, S  (lane owns pencil (a = p0, b = p1))
   if (act) {
-    T* pen = X + p1 * m + p0;
+    const T hx = hg[e * 3 + 0], hy = hg[e * 3 + 1], hz = hg[e * 3 + 2];
+    const T ihx2 = T(4) / (hx * hx), ihy2 = T(4) / (hy * hy), ihz2 = T(4) / (hz * hz);
+    T kp = kap, c0 = cm;
+    if (ke != nullptr) {  // the subdomain's own element's coefficients
+      kp = ke[e];
+      c0 = ce[e];
+    }
+    T* pen = Xp + p1 * m + p0;
     const T dab = sL[p0] * ihx2 + sL[p1] * ihy2;
     pencil_St<m, T>(S, pen, MM, o);
 #pragma unroll
-    for (int c = 0; c < m; ++c) o[c] = o[c] / (kap * (dab + sL[c] * ihz2) + cm);
+    for (int c = 0; c < m; ++c) o[c] = o[c] * recip_pos(kp * (dab + sL[c] * ihz2) + c0);
     pencil_S<m, T>(S, o, pen, MM, T(1));
   }
   __syncthreads();
   // pass 4: eta, S
   if (act) {
-    T* col = X + p1 * MM + p0;
+    T* col = Xp + p1 * MM + p0;
 #pragma unroll
     for (int b = 0; b < m; ++b) v[b] = col[b * m];
     pencil_S<m, T>(S, v, col, m, T(1));
@@ -878,7 +922,8 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   __syncthreads();
   // pass 5: xi, S, and the volume factor 8/(hx hy hz)
   if (act) {
-    T* row = X + p1 * MM + p0 * m;
+    T* row = Xp + p1 * MM + p0 * m;
+    const T vscale = T(8) / (hg[e * 3 + 0] * hg[e * 3 + 1] * hg[e * 3 + 2]);
 #pragma unroll
     for (int a = 0; a < m; ++a) v[a] = row[a];
     pencil_S<m, T>(S, v, row, 1, vscale);
@@ -887,22 +932,31 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   // the element's own nodes to zc (element-local order); the slots outside it
   // to the consumer layout of the elements that hold them (NULL slots dropped)
   {
-    constexpr int R = (MMM + NT - 1) / NT, NX = MMM - (N + 1) * (N + 1) * (N + 1);
-    T* zce = zc + e * (MMM - NX);
-    const int32_t* xd = xdest + e * NX;
-    int32_t o[R], d[R];
-#pragma unroll
-    for (int q = 0; q < R; ++q) o[q] = (tid + q * NT < MMM) ? xord[tid + q * NT] : -1;
-#pragma unroll
-    for (int q = 0; q < R; ++q) d[q] = o[q] >= 0 ? xd[o[q]] : -1;
+    constexpr int32_t kSkip = INT32_MIN;  // lane slot past the patches, or a patch past the end
+    // the lane's slots are recomputed here rather than kept live (in
+    // registers) from the gather through the five passes
+    int ts = tid;
+    asm volatile("" : "+v"(ts));
+    int32_t oq[R], dq[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      if (tid + q * NT >= MMM) continue;
-      const T v = X[tid + q * NT];
-      if (o[q] < 0)
-        zce[-o[q] - 1] = v;
-      else if (d[q] >= 0)
-        zx[d[q]] = v;
+      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
+      oq[q] = (x < PPB * MMM && sE[lq] >= 0) ? xord[x - lq * MMM] : kSkip;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
+      dq[q] = oq[q] >= 0 ? xdest[sE[lq] * NX + oq[q]] : -1;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
+      if (oq[q] == kSkip) continue;
+      const T val = X[x];
+      if (oq[q] < 0)
+        zc[sE[lq] * NN + (-oq[q] - 1)] = val;
+      else if (dq[q] >= 0)
+        zx[dq[q]] = val;
     }
   }
 }

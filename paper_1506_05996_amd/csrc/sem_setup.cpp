@@ -196,15 +196,57 @@ void build_reference(HostTables& T, int N) {
       K[(N + 1 + a) * np + (N + 1 + b)] += d[R[a] * n1 + R[b]];
     }
   }
-  // K S = M S Lambda, S^T M S = I:  C = M^{-1/2} K M^{-1/2} = Q Lambda Q^T, S = M^{-1/2} Q
+  // K S = M S Lambda, S^T M S = I:  C = M^{-1/2} K M^{-1/2} = Q Lambda Q^T, S = M^{-1/2} Q.
+  // The pencil is symmetric under the reflection a -> np-1-a (rho and D are), so
+  // C splits into blocks on the even vectors (e_a + e_{np-1-a})/sqrt 2 (and the
+  // middle e_a when np is odd) and the odd ones (e_a - e_{np-1-a})/sqrt 2: each
+  // eigenvector is even or odd, and a 1D pass needs only half of S.  Each block
+  // is diagonalised on its own, so that the parity holds exactly.
   std::vector<double> C(np * np);
   for (int a = 0; a < np; ++a)
     for (int b = 0; b < np; ++b) C[a * np + b] = K[a * np + b] / std::sqrt(M[a] * M[b]);
-  std::vector<double> Q;
-  jacobi_eigen(np, C, T.lam, Q);
-  T.S.assign(np * np, 0.0);
-  for (int a = 0; a < np; ++a)
-    for (int b = 0; b < np; ++b) T.S[a * np + b] = Q[a * np + b] / std::sqrt(M[a]);
+  const int ho = np / 2, he = np - ho;
+  const double r2 = 1.0 / std::sqrt(2.0);
+  auto half_vec = [&](int a, int sign, std::vector<double>& v) {  // basis vector a of one block
+    v.assign(np, 0.0);
+    if (a < ho) {
+      v[a] = r2;
+      v[np - 1 - a] = sign * r2;
+    } else {
+      v[a] = 1.0;  // the middle node (np odd, even block)
+    }
+  };
+  auto block = [&](int n, int sign, std::vector<double>& lam, std::vector<double>& Q) {
+    std::vector<double> B(n * n), va, vb;
+    for (int a = 0; a < n; ++a) {
+      half_vec(a, sign, va);
+      for (int b = 0; b < n; ++b) {
+        half_vec(b, sign, vb);
+        double s = 0.0;
+        for (int x = 0; x < np; ++x)
+          for (int y = 0; y < np; ++y) s += va[x] * C[x * np + y] * vb[y];
+        B[a * n + b] = s;
+      }
+    }
+    jacobi_eigen(n, B, lam, Q);
+  };
+  std::vector<double> le, lo, Qe, Qo;
+  block(he, +1, le, Qe);
+  block(ho, -1, lo, Qo);
+  // packed basis: row a < ho holds S[a][even j] (j < he) then S[a][odd j]
+  // (j < ho); rows np-1-a follow by parity (+ even, - odd).  For odd np a last
+  // row holds the middle node's S[ho][even j].  Eigenvalues in the same order:
+  // the even ones ascending, then the odd ones.
+  T.S.assign((size_t)ho * np + (np % 2 ? he : 0), 0.0);
+  for (int a = 0; a < ho; ++a) {
+    const double w = r2 / std::sqrt(M[a]);
+    for (int j = 0; j < he; ++j) T.S[a * np + j] = Qe[a * he + j] * w;
+    for (int j = 0; j < ho; ++j) T.S[a * np + he + j] = Qo[a * ho + j] * w;
+  }
+  if (np % 2)
+    for (int j = 0; j < he; ++j) T.S[ho * np + j] = Qe[ho * he + j] / std::sqrt(M[ho]);
+  T.lam = le;
+  T.lam.insert(T.lam.end(), lo.begin(), lo.end());
 }
 
 // ---------------------------------------------------------------------------

@@ -93,5 +93,10 @@ def test_amg_with_element_coefficients_and_partial_dirichlet():
     b[dirichlet.astype(bool)] = 0.0
     P_exact = Problem(m.vtx, m.hex, 2, dirichlet=dirichlet, kappa=kap)
     ue, _, _, _ = P_exact.solve(b, rtol=1e-13)
-    xs, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13)
+    # 1e-13 sits on the FP64 floor of this problem's true residual (its
+    # minimum over 1,000 iterations is 0.9-1.0e-13, whichever rounding the
+    # patch solves take), so the solve may stop just above the target without
+    # converging: accept the floor, and hold the solution to the oracle's
+    xs, info = M.solve(torch.tensor(b, device=dev), rtol=1e-13, raise_on_noconv=False)
+    assert info["rel_residual"] <= 2e-13
     assert rel_l2(xs.cpu().numpy(), ue) <= 1e-10
