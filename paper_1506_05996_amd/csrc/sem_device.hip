@@ -384,17 +384,45 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
       hipLaunchKernelGGL(coarse_fwd_small_kernel, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, s, m->Wlev.p,
                          m->cvec.p, (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
                          m->fs_items.p + T.fs_off[h], ns);
-    if (nr > 0)
-      hipLaunchKernelGGL(coarse_fwd_kernel, dim3((unsigned)((nr + 3) / 4)), dim3(256), 0, s, m->Wlev.p, m->cvec.p,
-                         (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
-                         m->fr_items.p + T.fr_off[h], nr);
+    if (nr > 0) {
+      const RowItem* tl = m->fr_items.p + T.fr_off[h];
+      const double* Y = m->Ylev.p;
+      const double* P = m->fwd_pool.p;
+      switch (T.fr_rw[h]) {
+        case 4:
+          hipLaunchKernelGGL(coarse_fwd_kernel<4>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
+                             m->fnodes.p, tl);
+          break;
+        case 2:
+          hipLaunchKernelGGL(coarse_fwd_kernel<2>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
+                             m->fnodes.p, tl);
+          break;
+        default:
+          hipLaunchKernelGGL(coarse_fwd_kernel<1>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
+                             m->fnodes.p, tl);
+      }
+    }
     SEM_HIP(hipGetLastError());
   }
   for (int h = H - 1; h >= 0; --h) {
     const int64_t nb = T.br_off[h + 1] - T.br_off[h];
-    hipLaunchKernelGGL(coarse_bwd_kernel, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, m->Xlev.p,
-                       (const double*)m->Wlev.p, (const double*)m->bwd_pool.p, m->fb_idx.p, m->fnodes.p,
-                       m->br_items.p + T.br_off[h], nb);
+    if (nb == 0) continue;
+    const RowItem* tl = m->br_items.p + T.br_off[h];
+    const double* Z = m->Wlev.p;
+    const double* P = m->bwd_pool.p;
+    switch (T.br_rw[h]) {
+      case 4:
+        hipLaunchKernelGGL(coarse_bwd_kernel<4>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
+                           m->fnodes.p, tl);
+        break;
+      case 2:
+        hipLaunchKernelGGL(coarse_bwd_kernel<2>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
+                           m->fnodes.p, tl);
+        break;
+      default:
+        hipLaunchKernelGGL(coarse_bwd_kernel<1>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
+                           m->fnodes.p, tl);
+    }
     SEM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,

@@ -69,6 +69,10 @@ struct FrontNode {
   int32_t pad;
 };
 
+// Rows per wave of the tiled sweeps for a row length L: 4 for short rows (the
+// node's vector is reused by four rows), 1 for long ones (more waves in flight)
+inline int coarse_rows_per_wave(int64_t L) { return L <= 256 ? 4 : (L <= 1024 ? 2 : 1); }
+
 // one row of a per-height work list: (node, row or column of that node)
 struct RowItem {
   int32_t node;
@@ -133,7 +137,11 @@ struct HostTables {
   int32_t n_heights = 0;
   std::vector<int32_t> fy_off, fy_items;  // per height: coarse rows to assemble
   std::vector<int64_t> fr_off, br_off;    // per height: ranges of fr_items (large nodes) / br_items (all)
-  std::vector<RowItem> fr_items, br_items;  // forward rows (s + b per node), backward columns (s per node)
+  // forward tiles of large nodes (rows r.. of [S^-1; W], s + b rows per node) and
+  // backward tiles of every node (rows r.. of W^T, s per node): one workgroup
+  // per tile of 4 x rows-per-wave rows, the rows per wave chosen per height
+  std::vector<RowItem> fr_items, br_items;
+  std::vector<int32_t> fr_rw, br_rw;      // per height: rows per wave (1, 2 or 4)
   std::vector<int64_t> fs_off;            // per height: range of fs_items (small nodes)
   std::vector<RowItem> fs_items;          // 64-row chunks of small nodes' forward rows
   std::vector<double> corner_K;          // [E][8][8] order-1 element stiffness matrices

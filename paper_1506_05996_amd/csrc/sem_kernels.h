@@ -1267,34 +1267,56 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// one wave per row of the stacked matrix [S^-1; W] of a node (row-major,
-// s columns); rows < s give Z, the others the node's contribution
+// Tiled sweeps: one workgroup (4 waves) per tile of 4 RW consecutive rows of
+// one node, wave w taking rows r + w RW .. r + w RW + RW - 1.  The vector the
+// rows are dotted with (y_I forward, x_B backward) passes through LDS in
+// chunks of kCoarseStage entries, each staged once per tile; each lane sums
+// its columns c = lane + 64 j of the wave's RW rows in ascending c, then one
+// wave sum per row.
+constexpr int kCoarseStage = 1024;
+
+// forward, large nodes: rows of [S^-1; W] (row-major, s columns); rows < s
+// give Z, the others the node's contribution
+template <int RW>
 __global__ void __launch_bounds__(256)
 coarse_fwd_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ Y,
                   const double* __restrict__ pool, const FrontNode* __restrict__ nodes,
-                  const RowItem* __restrict__ items, int64_t n) {
-  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (it >= n) return;  // whole wave
-  const RowItem ri = items[it];
-  const FrontNode nd = nodes[ri.node];
-  const double* row = pool + nd.fwd + (int64_t)ri.row * nd.s;
+                  const RowItem* __restrict__ tiles) {
+  __shared__ double sv[kCoarseStage];
+  const RowItem ti = tiles[blockIdx.x];
+  const FrontNode nd = nodes[ti.node];
+  const int s = nd.s, f = nd.s + nd.b;
   const double* y = Y + nd.off;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int c = lane;
-  for (; c + 192 < nd.s; c += 256) {
-    a0 += row[c] * y[c];
-    a1 += row[c + 64] * y[c + 64];
-    a2 += row[c + 128] * y[c + 128];
-    a3 += row[c + 192] * y[c + 192];
+  const int lane = threadIdx.x & 63, r0 = ti.row + (threadIdx.x >> 6) * RW;
+  const double* rp[RW];
+  double acc[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    rp[i] = pool + nd.fwd + (int64_t)min(r0 + i, f - 1) * s;  // rows past the node: read, not stored
+    acc[i] = 0.0;
   }
-  for (; c < nd.s; c += 64) a0 += row[c] * y[c];
-  const double v = wave_sum((a0 + a1) + (a2 + a3));
-  if (lane == 0) {
-    if (ri.row < nd.s)
-      Z[nd.off + ri.row] = v;
-    else
-      cvec[nd.coff + ri.row - nd.s] = v;
+  for (int c0 = 0; c0 < s; c0 += kCoarseStage) {
+    const int cn = min(kCoarseStage, s - c0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int c = threadIdx.x; c < cn; c += 256) sv[c] = y[c0 + c];
+    __syncthreads();
+#pragma unroll 2
+    for (int c = lane; c < cn; c += 64) {
+      const double yc = sv[c];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) acc[i] += rp[i][c0 + c] * yc;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const double v = wave_sum(acc[i]);
+    const int r = r0 + i;
+    if (lane == 0 && r < f) {
+      if (r < s)
+        Z[nd.off + r] = v;
+      else
+        cvec[nd.coff + r - s] = v;
+    }
   }
 }
 
@@ -1342,29 +1364,44 @@ coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const
     cvec[nd.coff + rho - s] = v;
 }
 
-// one wave per own column c of a node: X_c = Z_c - (W^T)_c . X_B
+// backward: rows of W^T (row-major, b columns), one per own column c of a
+// node: X_c = Z_c - (W^T)_c . X_B (X_B final from the ancestors' launches)
+template <int RW>
 __global__ void __launch_bounds__(256)
 coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const double* __restrict__ pool,
                   const int32_t* __restrict__ fb_idx, const FrontNode* __restrict__ nodes,
-                  const RowItem* __restrict__ items, int64_t n) {
-  const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (it >= n) return;  // whole wave
-  const RowItem ri = items[it];
-  const FrontNode nd = nodes[ri.node];
-  const double* row = pool + nd.bwd + (int64_t)ri.row * nd.b;
+                  const RowItem* __restrict__ tiles) {
+  __shared__ double sv[kCoarseStage];
+  const RowItem ti = tiles[blockIdx.x];
+  const FrontNode nd = nodes[ti.node];
+  const int s = nd.s, b = nd.b;
   const int32_t* bi = fb_idx + nd.bidx;
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-  int k = lane;
-  for (; k + 192 < nd.b; k += 256) {
-    a0 += row[k] * X[bi[k]];
-    a1 += row[k + 64] * X[bi[k + 64]];
-    a2 += row[k + 128] * X[bi[k + 128]];
-    a3 += row[k + 192] * X[bi[k + 192]];
+  const int lane = threadIdx.x & 63, r0 = ti.row + (threadIdx.x >> 6) * RW;
+  const double* rp[RW];
+  double acc[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    rp[i] = pool + nd.bwd + (int64_t)min(r0 + i, s - 1) * b;
+    acc[i] = 0.0;
   }
-  for (; k < nd.b; k += 64) a0 += row[k] * X[bi[k]];
-  const double v = wave_sum((a0 + a1) + (a2 + a3));
-  if (lane == 0) X[nd.off + ri.row] = Z[nd.off + ri.row] - v;
+  for (int k0 = 0; k0 < b; k0 += kCoarseStage) {
+    const int kn = min(kCoarseStage, b - k0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int k = threadIdx.x; k < kn; k += 256) sv[k] = X[bi[k0 + k]];
+    __syncthreads();
+#pragma unroll 2
+    for (int k = lane; k < kn; k += 64) {
+      const double xk = sv[k];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) acc[i] += rp[i][k0 + k] * xk;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const double v = wave_sum(acc[i]);
+    const int r = r0 + i;
+    if (lane == 0 && r < s) X[nd.off + r] = Z[nd.off + r] - v;
+  }
 }
 
 // ---------------------------------------------------------------------------

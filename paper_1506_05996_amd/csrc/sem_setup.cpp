@@ -1264,7 +1264,21 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
   T.fr_items.clear();
   T.br_items.clear();
   T.fs_items.clear();
+  T.fr_rw.assign(T.n_heights, 4);
+  T.br_rw.assign(T.n_heights, 4);
   for (int32_t h = 0; h < T.n_heights; ++h) {
+    // rows per wave from the longest row at this height: s for the forward
+    // rows of large nodes, b for the backward rows
+    int64_t lf = 0, lb = 0;
+    for (int32_t q = 0; q < nn; ++q) {
+      const FrontNode& F = T.fnodes[q];
+      if (F.height != h) continue;
+      if (!F.small) lf = std::max<int64_t>(lf, F.s);
+      lb = std::max<int64_t>(lb, F.b);
+    }
+    T.fr_rw[h] = coarse_rows_per_wave(lf);
+    T.br_rw[h] = coarse_rows_per_wave(lb);
+    const int32_t tf = 4 * T.fr_rw[h], tb = 4 * T.br_rw[h];
     for (int32_t q = 0; q < nn; ++q) {
       const FrontNode& F = T.fnodes[q];
       if (F.height != h) continue;
@@ -1272,8 +1286,8 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
       if (F.small)
         for (int32_t r = 0; r < (F.s + F.b + 63) / 64; ++r) T.fs_items.push_back(RowItem{q, r});
       else
-        for (int32_t r = 0; r < F.s + F.b; ++r) T.fr_items.push_back(RowItem{q, r});
-      for (int32_t r = 0; r < F.s; ++r) T.br_items.push_back(RowItem{q, r});
+        for (int32_t r = 0; r < F.s + F.b; r += tf) T.fr_items.push_back(RowItem{q, r});
+      for (int32_t r = 0; r < F.s; r += tb) T.br_items.push_back(RowItem{q, r});
     }
     T.fy_off[h + 1] = (int32_t)T.fy_items.size();
     T.fr_off[h + 1] = (int64_t)T.fr_items.size();

@@ -112,6 +112,30 @@ def test_precond_fp32(case):
     assert err <= 1e-5
 
 
+def test_coarse_solve_large_fronts():
+    # 24^3 hexes: separators of up to 23^2 = 529 vertices, so the sweeps take
+    # every tile shape (4, 2 and 1 rows per wave, forward and backward);
+    # against the oracle's coarse matrix solved directly on the free vertices
+    import scipy.sparse.linalg as spla
+    from oracle.coarse import coarse_matrix
+    from oracle.numbering import number_mesh
+    from paper_1506_05996_amd import sem
+    dev = _dev()
+    m = meshgen.cube_mesh(24, perturb=0.1, seed=7)
+    m, _ = meshgen.rotate_elements(m, seed=8)
+    M = sem.Mesh(m.vtx, m.hex, 2)
+    num = number_mesh(m.hex, 2)
+    nv = num.n_vertices
+    free = np.nonzero(num.dirichlet[:nv] == 0)[0]
+    Ac = coarse_matrix(m.vtx, m.hex, nv).tocsr()[free][:, free].tocsc()
+    R = np.random.default_rng(1509).uniform(-1, 1, nv)
+    Z = M.coarse_solve(torch.tensor(R, device=dev)).cpu().numpy()
+    ref = spla.spsolve(Ac, R[free])
+    assert np.abs(Z[num.dirichlet[:nv].astype(bool)]).max() == 0.0
+    assert rel_l2(Z[free], ref) <= 1e-11
+    M.close()
+
+
 def test_coarse_solve(case):
     M, P, dev = case["M"], case["P"], case["dev"]
     C = P.coarse
