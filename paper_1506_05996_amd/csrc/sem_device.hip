@@ -370,6 +370,37 @@ void fdm_and_restrict(sem_mesh m, const T* r, bool fine, bool coarse, hipStream_
   }
 }
 
+// one tiled launch of the forward (large nodes) or backward sweep at a height
+template <int RW, bool SPLIT>
+void launch_coarse_fwd_t(sem_mesh m, hipStream_t s, const RowItem* tiles, int64_t n) {
+  hipLaunchKernelGGL((coarse_fwd_kernel<RW, SPLIT>), dim3((unsigned)n), dim3(256), 0, s, m->Wlev.p, m->cvec.p,
+                     (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p, tiles);
+}
+
+template <int RW, bool SPLIT>
+void launch_coarse_bwd_t(sem_mesh m, hipStream_t s, const RowItem* tiles, int64_t n) {
+  hipLaunchKernelGGL((coarse_bwd_kernel<RW, SPLIT>), dim3((unsigned)n), dim3(256), 0, s, m->Xlev.p,
+                     (const double*)m->Wlev.p, (const double*)m->bwd_pool.p, m->fb_idx.p, m->fnodes.p, tiles);
+}
+
+void launch_coarse_fwd(sem_mesh m, hipStream_t s, const CoarseTileShape& t, const RowItem* tiles, int64_t n) {
+  if (t.rw == 4)
+    launch_coarse_fwd_t<4, false>(m, s, tiles, n);
+  else if (!t.split)
+    launch_coarse_fwd_t<2, false>(m, s, tiles, n);
+  else
+    launch_coarse_fwd_t<2, true>(m, s, tiles, n);
+}
+
+void launch_coarse_bwd(sem_mesh m, hipStream_t s, const CoarseTileShape& t, const RowItem* tiles, int64_t n) {
+  if (t.rw == 4)
+    launch_coarse_bwd_t<4, false>(m, s, tiles, n);
+  else if (!t.split)
+    launch_coarse_bwd_t<2, false>(m, s, tiles, n);
+  else
+    launch_coarse_bwd_t<2, true>(m, s, tiles, n);
+}
+
 // Rlev (coarse order) -> Zv (vertex order): nested-dissection sweeps
 void coarse_sweeps(sem_mesh m, hipStream_t s) {
   const HostTables& T = m->T;
@@ -377,52 +408,23 @@ void coarse_sweeps(sem_mesh m, hipStream_t s) {
   for (int h = 0; h < H; ++h) {
     const int64_t ny = T.fy_off[h + 1] - T.fy_off[h], nr = T.fr_off[h + 1] - T.fr_off[h];
     const int64_t ns = T.fs_off[h + 1] - T.fs_off[h];
-    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)blocks_for(8 * ny)), dim3(kGS), 0, s, m->Ylev.p,
-                       (const double*)m->Rlev.p, (const double*)m->cvec.p, m->ct_off.p, m->ct_pos.p,
-                       m->fy_items.p + T.fy_off[h], ny);
+    if (ny > 0)  // rows of the large nodes (small nodes assemble their own)
+      hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)blocks_for(8 * ny)), dim3(kGS), 0, s, m->Ylev.p,
+                         (const double*)m->Rlev.p, (const double*)m->cvec.p, m->ct_off.p, m->ct_pos.p,
+                         m->fy_items.p + T.fy_off[h], ny);
     if (ns > 0)
       hipLaunchKernelGGL(coarse_fwd_small_kernel, dim3((unsigned)((ns + 3) / 4)), dim3(256), 0, s, m->Wlev.p,
-                         m->cvec.p, (const double*)m->Ylev.p, (const double*)m->fwd_pool.p, m->fnodes.p,
+                         m->cvec.p, (const double*)m->Rlev.p, (const int32_t*)m->ct_off.p,
+                         (const int32_t*)m->ct_pos.p, (const double*)m->fwd_pool.p, m->fnodes.p,
                          m->fs_items.p + T.fs_off[h], ns);
-    if (nr > 0) {
-      const RowItem* tl = m->fr_items.p + T.fr_off[h];
-      const double* Y = m->Ylev.p;
-      const double* P = m->fwd_pool.p;
-      switch (T.fr_rw[h]) {
-        case 4:
-          hipLaunchKernelGGL(coarse_fwd_kernel<4>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
-                             m->fnodes.p, tl);
-          break;
-        case 2:
-          hipLaunchKernelGGL(coarse_fwd_kernel<2>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
-                             m->fnodes.p, tl);
-          break;
-        default:
-          hipLaunchKernelGGL(coarse_fwd_kernel<1>, dim3((unsigned)nr), dim3(256), 0, s, m->Wlev.p, m->cvec.p, Y, P,
-                             m->fnodes.p, tl);
-      }
-    }
+    if (nr > 0)
+      launch_coarse_fwd(m, s, T.fr_shape[h], m->fr_items.p + T.fr_off[h], nr);
     SEM_HIP(hipGetLastError());
   }
   for (int h = H - 1; h >= 0; --h) {
     const int64_t nb = T.br_off[h + 1] - T.br_off[h];
     if (nb == 0) continue;
-    const RowItem* tl = m->br_items.p + T.br_off[h];
-    const double* Z = m->Wlev.p;
-    const double* P = m->bwd_pool.p;
-    switch (T.br_rw[h]) {
-      case 4:
-        hipLaunchKernelGGL(coarse_bwd_kernel<4>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
-                           m->fnodes.p, tl);
-        break;
-      case 2:
-        hipLaunchKernelGGL(coarse_bwd_kernel<2>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
-                           m->fnodes.p, tl);
-        break;
-      default:
-        hipLaunchKernelGGL(coarse_bwd_kernel<1>, dim3((unsigned)nb), dim3(256), 0, s, m->Xlev.p, Z, P, m->fb_idx.p,
-                           m->fnodes.p, tl);
-    }
+    launch_coarse_bwd(m, s, T.br_shape[h], m->br_items.p + T.br_off[h], nb);
     SEM_HIP(hipGetLastError());
   }
   hipLaunchKernelGGL(coarse_scatter_kernel, dim3((unsigned)blocks_for(T.V)), dim3(kGS), 0, s, m->Zv.p, m->Xlev.p,

@@ -69,9 +69,20 @@ struct FrontNode {
   int32_t pad;
 };
 
-// Rows per wave of the tiled sweeps for a row length L: 4 for short rows (the
-// node's vector is reused by four rows), 1 for long ones (more waves in flight)
-inline int coarse_rows_per_wave(int64_t L) { return L <= 256 ? 4 : (L <= 1024 ? 2 : 1); }
+// Tile shape of the sweeps for a row length L: rows per wave (4 for short
+// rows, whose node vector serves four rows; 2 beyond 256) and, beyond 1024
+// columns, rows split across the workgroup's 4 waves (more waves in flight
+// for the long rows of the upper heights).  A tile holds rw rows when split,
+// else 4 rw.
+struct CoarseTileShape {
+  int32_t rw;
+  int32_t split;
+};
+inline CoarseTileShape coarse_tile_shape(int64_t L) {
+  if (L <= 256) return CoarseTileShape{4, 0};
+  return CoarseTileShape{2, L > 1024 ? 1 : 0};
+}
+inline int32_t coarse_tile_rows(const CoarseTileShape& t) { return t.split ? t.rw : 4 * t.rw; }
 
 // one row of a per-height work list: (node, row or column of that node)
 struct RowItem {
@@ -135,13 +146,13 @@ struct HostTables {
   int64_t ustack_size = 0;               // largest sum of pending update matrices (set-up)
   int32_t max_front = 0;                 // largest s + b
   int32_t n_heights = 0;
-  std::vector<int32_t> fy_off, fy_items;  // per height: coarse rows to assemble
+  std::vector<int32_t> fy_off, fy_items;  // per height: coarse rows of large nodes to assemble
   std::vector<int64_t> fr_off, br_off;    // per height: ranges of fr_items (large nodes) / br_items (all)
   // forward tiles of large nodes (rows r.. of [S^-1; W], s + b rows per node) and
   // backward tiles of every node (rows r.. of W^T, s per node): one workgroup
-  // per tile of 4 x rows-per-wave rows, the rows per wave chosen per height
+  // per tile, the tile shape chosen per height
   std::vector<RowItem> fr_items, br_items;
-  std::vector<int32_t> fr_rw, br_rw;      // per height: rows per wave (1, 2 or 4)
+  std::vector<CoarseTileShape> fr_shape, br_shape;  // per height: tile shape of the forward / backward launch
   std::vector<int64_t> fs_off;            // per height: range of fs_items (small nodes)
   std::vector<RowItem> fs_items;          // 64-row chunks of small nodes' forward rows
   std::vector<double> corner_K;          // [E][8][8] order-1 element stiffness matrices

@@ -1267,27 +1267,69 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Tiled sweeps: one workgroup (4 waves) per tile of 4 RW consecutive rows of
-// one node, wave w taking rows r + w RW .. r + w RW + RW - 1.  The vector the
-// rows are dotted with (y_I forward, x_B backward) passes through LDS in
-// chunks of kCoarseStage entries, each staged once per tile; each lane sums
-// its columns c = lane + 64 j of the wave's RW rows in ascending c, then one
-// wave sum per row.
+// Tiled sweeps: one workgroup (4 waves) per tile of rows of one node.  Not
+// split: a tile of 4 RW consecutive rows, wave w taking rows r + w RW ..
+// r + w RW + RW - 1, each lane its columns c = lane + 64 j.  Split (rows
+// longer than 1024): a tile of RW rows shared by the 4 waves, wave w taking
+// the column blocks c = 64 w + lane + 256 j, the 4 partial sums of a row
+// added in wave order through LDS.  The vector the rows are dotted with (y_I
+// forward, x_B backward) passes through LDS in chunks of kCoarseStage entries
+// (a multiple of 256), each staged once per tile; sums run in ascending c
+// within a lane, then a wave sum per row.
 constexpr int kCoarseStage = 1024;
+
+// the wave's RW dot products against the staged vector; returns them summed over the wave (lane 0 holds them)
+template <int RW, bool SPLIT>
+__device__ __forceinline__ void coarse_tile_dots(const double* const (&rp)[RW], double (&acc)[RW], int len,
+                                                 const double* __restrict__ stage_src,
+                                                 const int32_t* __restrict__ gather_idx, double* sv) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int cfirst = SPLIT ? 64 * wave + lane : lane, cstep = SPLIT ? 256 : 64;
+  for (int c0 = 0; c0 < len; c0 += kCoarseStage) {
+    const int cn = min(kCoarseStage, len - c0);
+    __syncthreads();  // the previous chunk is consumed
+    for (int c = threadIdx.x; c < cn; c += 256)
+      sv[c] = gather_idx != nullptr ? stage_src[gather_idx[c0 + c]] : stage_src[c0 + c];
+    __syncthreads();
+#pragma unroll 2
+    for (int c = cfirst; c < cn; c += cstep) {
+      const double vc = sv[c];
+#pragma unroll
+      for (int i = 0; i < RW; ++i) acc[i] += rp[i][c0 + c] * vc;
+    }
+  }
+}
+
+// row sums of a tile: not split, each wave's own rows; split, the 4 waves'
+// partial sums of the shared rows in wave order (thread 0 holds them)
+template <int RW, bool SPLIT>
+__device__ __forceinline__ void coarse_tile_reduce(double (&acc)[RW], double (*sp)[RW]) {
+#pragma unroll
+  for (int i = 0; i < RW; ++i) acc[i] = wave_sum(acc[i]);
+  if constexpr (SPLIT) {
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int i = 0; i < RW; ++i) sp[threadIdx.x >> 6][i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int i = 0; i < RW; ++i) acc[i] = ((sp[0][i] + sp[1][i]) + sp[2][i]) + sp[3][i];
+  }
+}
 
 // forward, large nodes: rows of [S^-1; W] (row-major, s columns); rows < s
 // give Z, the others the node's contribution
-template <int RW>
+template <int RW, bool SPLIT>
 __global__ void __launch_bounds__(256)
 coarse_fwd_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ Y,
                   const double* __restrict__ pool, const FrontNode* __restrict__ nodes,
                   const RowItem* __restrict__ tiles) {
   __shared__ double sv[kCoarseStage];
+  __shared__ double sp[4][RW];
   const RowItem ti = tiles[blockIdx.x];
   const FrontNode nd = nodes[ti.node];
   const int s = nd.s, f = nd.s + nd.b;
-  const double* y = Y + nd.off;
-  const int lane = threadIdx.x & 63, r0 = ti.row + (threadIdx.x >> 6) * RW;
+  const int r0 = SPLIT ? ti.row : ti.row + (threadIdx.x >> 6) * RW;
   const double* rp[RW];
   double acc[RW];
 #pragma unroll
@@ -1295,29 +1337,18 @@ coarse_fwd_kernel(double* __restrict__ Z, double* __restrict__ cvec, const doubl
     rp[i] = pool + nd.fwd + (int64_t)min(r0 + i, f - 1) * s;  // rows past the node: read, not stored
     acc[i] = 0.0;
   }
-  for (int c0 = 0; c0 < s; c0 += kCoarseStage) {
-    const int cn = min(kCoarseStage, s - c0);
-    __syncthreads();  // the previous chunk is consumed
-    for (int c = threadIdx.x; c < cn; c += 256) sv[c] = y[c0 + c];
-    __syncthreads();
-#pragma unroll 2
-    for (int c = lane; c < cn; c += 64) {
-      const double yc = sv[c];
+  coarse_tile_dots<RW, SPLIT>(rp, acc, s, Y + nd.off, nullptr, sv);
+  coarse_tile_reduce<RW, SPLIT>(acc, sp);
+  if (SPLIT ? threadIdx.x == 0 : (threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int i = 0; i < RW; ++i) acc[i] += rp[i][c0 + c] * yc;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    const double v = wave_sum(acc[i]);
-    const int r = r0 + i;
-    if (lane == 0 && r < f) {
+    for (int i = 0; i < RW; ++i) {
+      const int r = r0 + i;
+      if (r >= f) break;
       if (r < s)
-        Z[nd.off + r] = v;
+        Z[nd.off + r] = acc[i];
       else
-        cvec[nd.coff + r - s] = v;
+        cvec[nd.coff + r - s] = acc[i];
     }
-  }
 }
 
 // value of v held by lane l (l wave-uniform)
@@ -1329,9 +1360,13 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 
 // small nodes (s <= 128): one lane per row of [S^-1; W] (column-major,
 // leading dimension s + b), 64-row chunks; y sits in two registers per lane
-// and is broadcast with readlane; matrix loads go out eight at a time
+// and is broadcast with readlane; matrix loads go out eight at a time.  Each
+// wave assembles the node's y itself (lane i: y_i = R_i minus the listed
+// contributions of the descendants, in list order), so heights with only
+// small nodes need no assembly launch.
 __global__ void __launch_bounds__(256)
-coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ Y,
+coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const double* __restrict__ R,
+                        const int32_t* __restrict__ ct_off, const int32_t* __restrict__ ct_pos,
                         const double* __restrict__ pool, const FrontNode* __restrict__ nodes,
                         const RowItem* __restrict__ items, int64_t n) {
   const int64_t it = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * 4 + (threadIdx.x >> 6)));
@@ -1343,9 +1378,13 @@ coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const
   const int rho = ri.row * 64 + lane;
   const int rr = rho < f ? rho : f - 1;
   const double* M = pool + nd.fwd + rr;
-  const double* y = Y + nd.off;
-  const double y0 = lane < s ? y[lane] : 0.0;
-  const double y1 = lane + 64 < s ? y[lane + 64] : 0.0;
+  auto y_row = [&](int64_t g) {  // assembled y of coarse row g (contributions written by earlier launches)
+    double a = 0.0;
+    for (int32_t q = ct_off[g]; q < ct_off[g + 1]; ++q) a += cvec[ct_pos[q]];
+    return R[g] - a;
+  };
+  const double y0 = lane < s ? y_row(nd.off + lane) : 0.0;
+  const double y1 = lane + 64 < s ? y_row(nd.off + lane + 64) : 0.0;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int c0 = 0; c0 < s; c0 += 8) {
     double mv[8];
@@ -1366,17 +1405,17 @@ coarse_fwd_small_kernel(double* __restrict__ Z, double* __restrict__ cvec, const
 
 // backward: rows of W^T (row-major, b columns), one per own column c of a
 // node: X_c = Z_c - (W^T)_c . X_B (X_B final from the ancestors' launches)
-template <int RW>
+template <int RW, bool SPLIT>
 __global__ void __launch_bounds__(256)
 coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const double* __restrict__ pool,
                   const int32_t* __restrict__ fb_idx, const FrontNode* __restrict__ nodes,
                   const RowItem* __restrict__ tiles) {
   __shared__ double sv[kCoarseStage];
+  __shared__ double sp[4][RW];
   const RowItem ti = tiles[blockIdx.x];
   const FrontNode nd = nodes[ti.node];
   const int s = nd.s, b = nd.b;
-  const int32_t* bi = fb_idx + nd.bidx;
-  const int lane = threadIdx.x & 63, r0 = ti.row + (threadIdx.x >> 6) * RW;
+  const int r0 = SPLIT ? ti.row : ti.row + (threadIdx.x >> 6) * RW;
   const double* rp[RW];
   double acc[RW];
 #pragma unroll
@@ -1384,24 +1423,15 @@ coarse_bwd_kernel(double* __restrict__ X, const double* __restrict__ Z, const do
     rp[i] = pool + nd.bwd + (int64_t)min(r0 + i, s - 1) * b;
     acc[i] = 0.0;
   }
-  for (int k0 = 0; k0 < b; k0 += kCoarseStage) {
-    const int kn = min(kCoarseStage, b - k0);
-    __syncthreads();  // the previous chunk is consumed
-    for (int k = threadIdx.x; k < kn; k += 256) sv[k] = X[bi[k0 + k]];
-    __syncthreads();
-#pragma unroll 2
-    for (int k = lane; k < kn; k += 64) {
-      const double xk = sv[k];
+  coarse_tile_dots<RW, SPLIT>(rp, acc, b, X, fb_idx + nd.bidx, sv);
+  coarse_tile_reduce<RW, SPLIT>(acc, sp);
+  if (SPLIT ? threadIdx.x == 0 : (threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int i = 0; i < RW; ++i) acc[i] += rp[i][k0 + k] * xk;
+    for (int i = 0; i < RW; ++i) {
+      const int r = r0 + i;
+      if (r >= s) break;
+      X[nd.off + r] = Z[nd.off + r] - acc[i];
     }
-  }
-#pragma unroll
-  for (int i = 0; i < RW; ++i) {
-    const double v = wave_sum(acc[i]);
-    const int r = r0 + i;
-    if (lane == 0 && r < s) X[nd.off + r] = Z[nd.off + r] - v;
-  }
 }
 
 // ---------------------------------------------------------------------------

@@ -1264,10 +1264,10 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
   T.fr_items.clear();
   T.br_items.clear();
   T.fs_items.clear();
-  T.fr_rw.assign(T.n_heights, 4);
-  T.br_rw.assign(T.n_heights, 4);
+  T.fr_shape.assign(T.n_heights, CoarseTileShape{4, 0});
+  T.br_shape.assign(T.n_heights, CoarseTileShape{4, 0});
   for (int32_t h = 0; h < T.n_heights; ++h) {
-    // rows per wave from the longest row at this height: s for the forward
+    // tile shapes from the longest row at this height: s for the forward
     // rows of large nodes, b for the backward rows
     int64_t lf = 0, lb = 0;
     for (int32_t q = 0; q < nn; ++q) {
@@ -1276,13 +1276,14 @@ void build_coarse_tree(HostTables& T, int leaf_max) {
       if (!F.small) lf = std::max<int64_t>(lf, F.s);
       lb = std::max<int64_t>(lb, F.b);
     }
-    T.fr_rw[h] = coarse_rows_per_wave(lf);
-    T.br_rw[h] = coarse_rows_per_wave(lb);
-    const int32_t tf = 4 * T.fr_rw[h], tb = 4 * T.br_rw[h];
+    T.fr_shape[h] = coarse_tile_shape(lf);
+    T.br_shape[h] = coarse_tile_shape(lb);
+    const int32_t tf = coarse_tile_rows(T.fr_shape[h]), tb = coarse_tile_rows(T.br_shape[h]);
     for (int32_t q = 0; q < nn; ++q) {
       const FrontNode& F = T.fnodes[q];
       if (F.height != h) continue;
-      for (int32_t r = 0; r < F.s; ++r) T.fy_items.push_back((int32_t)(F.off + r));
+      if (!F.small)  // small nodes assemble their y in the forward kernel
+        for (int32_t r = 0; r < F.s; ++r) T.fy_items.push_back((int32_t)(F.off + r));
       if (F.small)
         for (int32_t r = 0; r < (F.s + F.b + 63) / 64; ++r) T.fs_items.push_back(RowItem{q, r});
       else

@@ -112,16 +112,20 @@ def test_precond_fp32(case):
     assert err <= 1e-5
 
 
-def test_coarse_solve_large_fronts():
-    # 24^3 hexes: separators of up to 23^2 = 529 vertices, so the sweeps take
-    # every tile shape (4, 2 and 1 rows per wave, forward and backward);
-    # against the oracle's coarse matrix solved directly on the free vertices
+@pytest.mark.parametrize("k", [24, 36])
+def test_coarse_solve_large_fronts(k):
+    # k^3 hexes: separators of up to (k-1)^2 vertices, so the sweeps take the
+    # tile shapes of large fronts (24: 4 and 2 rows per wave; 36: also rows
+    # longer than 1024 split across a workgroup's waves), forward and
+    # backward; against the oracle's coarse matrix factorised directly on the
+    # free vertices
     import scipy.sparse.linalg as spla
     from oracle.coarse import coarse_matrix
     from oracle.numbering import number_mesh
     from paper_1506_05996_amd import sem
     dev = _dev()
-    m = meshgen.cube_mesh(24, perturb=0.1, seed=7)
+    print(f"[coarse large fronts] k={k}", flush=True)
+    m = meshgen.cube_mesh(k, perturb=0.1, seed=7)
     m, _ = meshgen.rotate_elements(m, seed=8)
     M = sem.Mesh(m.vtx, m.hex, 2)
     num = number_mesh(m.hex, 2)
@@ -130,7 +134,8 @@ def test_coarse_solve_large_fronts():
     Ac = coarse_matrix(m.vtx, m.hex, nv).tocsr()[free][:, free].tocsc()
     R = np.random.default_rng(1509).uniform(-1, 1, nv)
     Z = M.coarse_solve(torch.tensor(R, device=dev)).cpu().numpy()
-    ref = spla.spsolve(Ac, R[free])
+    lu = spla.splu(Ac, permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0, options=dict(SymmetricMode=True))
+    ref = lu.solve(R[free])
     assert np.abs(Z[num.dirichlet[:nv].astype(bool)]).max() == 0.0
     assert rel_l2(Z[free], ref) <= 1e-11
     M.close()
