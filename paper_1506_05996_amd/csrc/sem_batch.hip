@@ -324,7 +324,7 @@ struct sem_batch_s {
 
 namespace {
 
-unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>(8192, blocks_of(n)); }
+unsigned grid_for(int64_t n) { return (unsigned)std::min<int64_t>(65536, blocks_of(n)); }
 
 template <typename TA, typename TB>
 void seg_dot(sem_batch b, Group& g, const TA* x, const TB* y, hipStream_t s) {

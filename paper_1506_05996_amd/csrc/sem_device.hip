@@ -31,7 +31,10 @@ namespace sem {
 constexpr int kGS = 256;
 
 inline int64_t blocks_for(int64_t n, int t = kGS) { return std::max<int64_t>(1, (n + t - 1) / t); }
-inline int grid_stride_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), 8192); }
+// grid of the grid-stride streaming kernels: up to 65,536 workgroups (more
+// loads in flight than the 8,192 a stream of n_global doubles would need to
+// cover the chip once: the p/x update streams at 5.2 TB/s instead of 4.5)
+inline int grid_stride_blocks(int64_t n) { return (int)std::min<int64_t>(blocks_for(n), 65536); }
 
 // every pointer 16-byte aligned (the streaming kernels then move two entries per access)
 template <typename... P>
@@ -1792,7 +1795,7 @@ int sem_stream_bench(const double* a, double* b, double* c, int64_t n, int reps,
     const double bytes[3] = {16.0 * n, 24.0 * n, 8.0 * n};
     for (int q = 0; q < 3; ++q) gbs[q] = 0.0;
     // best over grid sizes (workgroups of 256 lanes), each timed over reps launches
-    for (int grid : {1024, 2048, 4096, 8192, 16384}) {
+    for (int grid : {1024, 2048, 4096, 8192, 16384, 32768, 65536}) {
       const int g = (int)std::min<int64_t>(grid, (n2 + 255) / 256);
       for (int q = 0; q < 3; ++q) {
         auto launch = [&]() {
