@@ -288,6 +288,24 @@ void apply_A(sem_mesh m, const T* u, T* y, hipStream_t s) {
   launch_gs<T>(m, y, s, nullptr, nullptr, u);
 }
 
+// the n partial sums in the work's dpart into scalar slot dst (dot_final mode
+// `mode`): through kRedBlocks chunk sums when there are many; a single launch
+// when there are at most kRedBlocks (the chunk sums would then copy them one
+// by one, so the result is the same bit for bit)
+void reduce_partials(sem_mesh m, int64_t n, int dst, int mode, hipStream_t s) {
+  if (n <= kRedBlocks) {
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.sc, (int)n,
+                       dst, mode);
+  } else {
+    const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
+    const int nb = (int)((n + chunk - 1) / chunk);
+    hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part,
+                       n, chunk);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dst, mode);
+  }
+  SEM_HIP(hipGetLastError());
+}
+
 // y = A u and u . y into the scalar slot dst (dot_final mode `mode`), the dot
 // product taken from the operator's own kernels (no extra pass over u and y)
 template <typename T>
@@ -295,12 +313,7 @@ void apply_A_dot(sem_mesh m, const T* u, T* y, int dst, int mode, hipStream_t s)
   const int64_t na = apply_A_elements<T>(m, u, y, s, m->wk.dpart);
   const int64_t ng = launch_gs<T>(m, y, s, u, m->wk.dpart + na, u);
   const int64_t n = na + ng;
-  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
-  const int nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
-                     chunk);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dst, mode);
-  SEM_HIP(hipGetLastError());
+  reduce_partials(m, n, dst, mode, s);
 }
 
 // --- fine and coarse preconditioner -----------------------------------------
@@ -658,12 +671,7 @@ void precond_dot(sem_mesh m, const T* r, T* z, int pc, int dot_dst, int dot_mode
     return;
   }
   const int64_t n = schwarz_sum<T>(m, z, fine, coarse ? (const double*)m->Zv.p : nullptr, s, r, m->wk.dpart);
-  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
-  const int nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
-                     chunk);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, dot_dst, dot_mode);
-  SEM_HIP(hipGetLastError());
+  reduce_partials(m, n, dot_dst, dot_mode, s);
 }
 
 // PCG's update of r fused with the coarse restriction (update_r_restrict_kernel),
@@ -693,12 +701,7 @@ void update_r_and_fork_coarse(sem_mesh m, T* r, const T* w, hipStream_t s) {
     default:
       throw Error{SEM_EUNSUPPORTED, "order not compiled"};
   }
-  const int64_t chunk = (n + kRedBlocks - 1) / kRedBlocks;
-  const int nb = (int)((n + chunk - 1) / chunk);
-  hipLaunchKernelGGL(sum_chunks_kernel, dim3(nb), dim3(kRedThreads), 0, s, (const double*)m->wk.dpart, m->wk.part, n,
-                     chunk);
-  hipLaunchKernelGGL(dot_final_kernel, dim3(1), dim3(kRedThreads), 0, s, m->wk.part, m->wk.sc, nb, 4, 0);
-  SEM_HIP(hipGetLastError());
+  reduce_partials(m, n, 4, 0, s);
   const HostTables& H = m->T;
   ensure_side_stream(m);
   hipStream_t sc = m->side_stream;
