@@ -92,6 +92,10 @@ struct sem_mesh_s {
   int epb[2] = {0, 0};                    // operator tile (elements per workgroup) for FP64, FP32
   hipStream_t side_stream = nullptr;      // coarse chain of the preconditioner, beside the patch solves
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  // PCG's convergence check read back without draining the stream: r . r and
+  // the breakdown flag land in pinned host memory, signalled by ev_check
+  double* check_host = nullptr;
+  hipEvent_t ev_check = nullptr;
   hipStream_t capture_stream = nullptr;
   // lumped mass m_N for the mass term of the operator (uploaded when c != 0),
   // and the right-hand side of a heat-equation step

@@ -949,6 +949,8 @@ void ensure_work(sem_mesh m, bool need32) {
   m->wk.part = m->part.p;
   m->wk.sc = m->sc.p;
   m->wk.dpart = m->dpart.p;
+  if (!m->check_host) SEM_HIP(hipHostMalloc((void**)&m->check_host, 4 * sizeof(double), hipHostMallocDefault));
+  if (!m->ev_check) SEM_HIP(hipEventCreateWithFlags(&m->ev_check, hipEventDisableTiming));
 }
 
 // --- static scratch of sem_pcg_solve_noalloc ------------------------------
@@ -1075,6 +1077,9 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int
   // the coarse solve starts beside the convergence check and the patch solves
   const bool fused = pc == SEM_PC_TWOSCALE && m->T.nc > 0 && !m->direct_coarse;
   bool coarse_pending = false;
+  // speculative ordering of the convergence check: needs the pinned read-back
+  // buffer (made by an ordinary solve's set-up; not in the allocation-free one)
+  const bool spec_ok = m->check_host != nullptr && m->ev_check != nullptr;
   while (k < max_iter) {
     apply_A_dot<T>(m, p, w, 1, 1, s);
     if (fused) {
@@ -1088,11 +1093,26 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int
     }
     ++k;
     pending_x = true;
+    bool z_ready = false;  // the preconditioner of this step already enqueued
     if (k % check_every == 0 || k == max_iter) {
-      // r^T r (slot 4) and the breakdown flag (slot 6) in one read-back
+      // r^T r (slot 4) and the breakdown flag (slot 6) in one read-back.  Far
+      // from the tolerance (the last r^T r above 100 tol^2) the step's
+      // preconditioner is enqueued before the host waits for them, so the GPU
+      // works through the round trip; if the check then ends the solve, that
+      // preconditioner was spent for nothing, which this margin makes rare
       double sc46[3];
-      SEM_HIP(hipMemcpyAsync(sc46, sc + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
-      SEM_HIP(hipStreamSynchronize(s));
+      if (spec_ok && k < max_iter && rr > 100.0 * tol2) {
+        SEM_HIP(hipMemcpyAsync(m->check_host, sc + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
+        SEM_HIP(hipEventRecord(m->ev_check, s));
+        precond_dot<T>(m, r, z, pc, 5, 2, s, coarse_pending);
+        coarse_pending = false;
+        z_ready = true;
+        SEM_HIP(hipEventSynchronize(m->ev_check));
+        std::memcpy(sc46, m->check_host, sizeof(sc46));
+      } else {
+        SEM_HIP(hipMemcpyAsync(sc46, sc + 4, sizeof(sc46), hipMemcpyDeviceToHost, s));
+        SEM_HIP(hipStreamSynchronize(s));
+      }
       rr = sc46[0];
       const double flag = sc46[2];
       if (st && st->history && st->history_len < st->history_cap)
@@ -1106,8 +1126,10 @@ int pcg_core(sem_mesh m, T* x, T* r, double bnorm2, double rr0, double rtol, int
         break;
       }
     }
-    precond_dot<T>(m, r, z, pc, 5, 2, s, coarse_pending);
-    coarse_pending = false;
+    if (!z_ready) {
+      precond_dot<T>(m, r, z, pc, 5, 2, s, coarse_pending);
+      coarse_pending = false;
+    }
     hipLaunchKernelGGL((update_px_kernel<T>), dim3(gb), dim3(kGS), 0, s, x, p, (const T*)z, (const double*)sc, n,
                        (int)aligned16(x, p, z));
     SEM_HIP(hipGetLastError());
@@ -1628,6 +1650,8 @@ int sem_mesh_destroy(sem_mesh m) {
     if (m->side_stream) (void)hipStreamDestroy(m->side_stream);
     if (m->ev_fork) (void)hipEventDestroy(m->ev_fork);
     if (m->ev_join) (void)hipEventDestroy(m->ev_join);
+    if (m->ev_check) (void)hipEventDestroy(m->ev_check);
+    if (m->check_host) (void)hipHostFree(m->check_host);
   }
   delete m;
   return SEM_OK;
