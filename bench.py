@@ -672,8 +672,8 @@ def main():
                     help="profiling run: K applications of the patch-solve preconditioner (FP64, then FP32), no timing")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); this build has no multi-GPU path",
-              file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library solves each mesh on one "
+              f"device and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch64":
