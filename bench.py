@@ -20,8 +20,9 @@ PCG solve to 1e-10, in FP64 and FP32-refined form (`heat` in the output).
 Further sections of the same line: `stream` (the device's copy/triad/read
 bandwidth with the library's own streaming kernels), `box20x8_N15` (20^3
 hexahedra stretched 8:1, N = 15: the FP64 and FP32 matrix-core operators
-against the vector kernel, PCG in FP64 and FP32-refined form), `batch64` (64
-instances of orders 3..8 solved in one batched call against one by one) and
+against the vector kernel, PCG in FP64 and FP32-refined form, the latter with
+inner tolerance 1e-3), `batch64` (64 instances of orders 3..8 solved in one
+batched call against one by one) and
 `cube4_N4` (the small cube: FP64 latency to 1e-8, the refined form to 1e-10
 with a sweep of its inner tolerance).  `cpu_baseline` times the FP64 oracle on
 the host: its operator on a sample of the 56^3 mesh, and its PCG.
@@ -412,7 +413,8 @@ def run_order15(args, dev):
     log(f"[bench] box20x8_N15 Ax fp64 {res['ax_fp64']}")
     log(f"[bench] box20x8_N15 Ax fp32 {res['ax_fp32']}")
     b, ue, mN = manufactured_rhs(M, mesh.lengths, dev)
-    res["pcg"] = solve_section(M, b, ue, mN, dict(rtol=1e-10, max_iter=4000, inner_rtol=args.inner_rtol,
+    res["inner_rtol"] = args.inner_rtol_n15
+    res["pcg"] = solve_section(M, b, ue, mN, dict(rtol=1e-10, max_iter=4000, inner_rtol=args.inner_rtol_n15,
                                                   max_outer=40), args.pcg_reps)
     log(f"[bench] box20x8_N15 PCG {res['pcg']}")
     M.close()
@@ -656,6 +658,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pcg-reps", type=int, default=3, help="timed solves per mode (median), after one warm-up")
     ap.add_argument("--inner-rtol", type=float, default=3e-3, help="refined form: tolerance of each FP32 inner solve")
+    ap.add_argument("--inner-rtol-n15", type=float, default=1e-3,
+                    help="refined form on the N = 15 box: tolerance of each FP32 inner solve")
     ap.add_argument("--no-serial", action="store_true", help="batch64: skip the one-by-one comparison")
     ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation run on the rod")
     ap.add_argument("--no-amg", action="store_true", help="skip the PCG runs with the AMG coarse solver")

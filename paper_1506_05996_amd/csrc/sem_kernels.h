@@ -1019,6 +1019,17 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
     for (int x = tid; x < 2 * n1; x += EPB * P) sPhi[x] = phi[x];
   }
   __syncthreads();
+  // I Z at (i, j, k) = Phi_0(t_k) zk0 + Phi_1(t_k) zk1, with zk0 / zk1 the
+  // bilinear interpolation in (i, j) of the vertex values on the faces k = 0 / N
+  double zk0 = 0.0, zk1 = 0.0;
+  if (Zv != nullptr) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double wij = sPhi[(c & 1) * n1 + i] * sPhi[(c >> 1) * n1 + j];
+      zk0 += wij * zv[c];
+      zk1 += wij * zv[c + 4];
+    }
+  }
   const T* xs = sX[le];
   const bool li0 = i == 1, li1 = i == N - 1, lj0 = j == 1, lj1 = j == N - 1;
   double dacc = 0.0;  // with dpart: this workgroup's share of rd . z over the interior nodes
@@ -1055,13 +1066,7 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
       }
     }
     const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
-    if (Zv != nullptr && (rr.w & kFlagOwned)) {
-      double acc = 0.0;
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        acc += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * zv[c];
-      v += (T)acc;
-    }
+    if (Zv != nullptr && (rr.w & kFlagOwned)) v += (T)(sPhi[k] * zk0 + sPhi[n1 + k] * zk1);
     int ai, aj, ak;
     unpack_coef(rr.y, ai, aj, ak);
     const int off = ai * i + aj * j + ak * k;
