@@ -77,7 +77,7 @@ struct sem_mesh_s {
   DBuf<float> G32, D32, w32, X832, tq32;
   // fine preconditioner
   // patch corrections: zo = [zc: E x (N+1)^3 own nodes | zx: E x nx consumer layout]
-  DBuf<int32_t> ip, xord, xdest;
+  DBuf<int32_t> ip, xdest;
   DBuf<double> S64, lam64, h64, zo64;
   DBuf<float> S32, lam32, h32, zo32;
   // coarse: vectors in coarse order (R, y, Z, X), vertex-order solution Zv,

@@ -322,7 +322,7 @@ void launch_fdm(sem_mesh m, const T* r, hipStream_t s) {
   T* zc = ZOp<T>(m);
   T* zx = zc + m->T.E * (int64_t)m->T.n1 * m->T.n1 * m->T.n1;
   hipLaunchKernelGGL((fdm_kernel<N, T>), dim3((unsigned)xcd_grid((m->T.E + fdm_ppb<N>() - 1) / fdm_ppb<N>())), dim3(fdm_threads<N>()), 0, s, r, zc, zx,
-                     m->ip.p, m->xord.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E,
+                     m->ip.p, m->xdest.p, Sp<T>(m), Lp<T>(m), Hp<T>(m), m->order.p, m->T.E,
                      (T)m->T.kappa, (T)m->T.cmass, m->per_elem ? KEp<T>(m) : nullptr,
                      m->per_elem ? CEp<T>(m) : nullptr);
   SEM_HIP(hipGetLastError());
@@ -886,7 +886,6 @@ void upload_all(sem_mesh m) {
   m->tq64.upload(tq.data(), tq.size());
   m->w64.alloc(T.w_size);
   m->ip.upload(T.ip.data(), T.ip.size());
-  m->xord.upload(T.xord.data(), T.xord.size());
   m->xdest.upload(T.xdest.data(), T.xdest.size());
   m->S64.upload(T.S.data(), T.S.size());
   m->lam64.upload(T.lam.data(), T.lam.size());

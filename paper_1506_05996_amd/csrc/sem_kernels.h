@@ -842,7 +842,7 @@ __device__ __forceinline__ void pencil_S(const T* __restrict__ Sp, const T (&v)[
 template <int N, typename T>
 __global__ void __launch_bounds__(fdm_threads<N>()) __attribute__((amdgpu_waves_per_eu(N <= 8 ? 8 : 4, 8)))
 fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, const int32_t* __restrict__ ip,
-           const int32_t* __restrict__ xord, const int32_t* __restrict__ xdest, const T* __restrict__ S,
+           const int32_t* __restrict__ xdest, const T* __restrict__ S,
            const T* __restrict__ lam, const T* __restrict__ hg, const int32_t* __restrict__ order, int64_t E,
            T kap, T cm, const T* __restrict__ ke, const T* __restrict__ ce) {
   constexpr int m = N + 3, MM = m * m, MMM = MM * m, PPB = fdm_ppb<N>(), NT = fdm_threads<N>();
@@ -929,34 +929,50 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     pencil_S<m, T>(S, v, row, 1, vscale);
   }
   __syncthreads();
-  // the element's own nodes to zc (element-local order); the slots outside it
-  // to the consumer layout of the elements that hold them (NULL slots dropped)
+  // Results out, driven by the destination: the element's own nodes to zc in
+  // element-local order (consecutive lanes, consecutive addresses), then the
+  // slots outside the element in their ordinal order (the whole first plane,
+  // 2m + 2(N+1) slots of each middle plane, the whole last plane), each to the
+  // consumer layout of the element that holds it (xdest read with consecutive
+  // addresses; NULL slots dropped).
   {
-    constexpr int32_t kSkip = INT32_MIN;  // lane slot past the patches, or a patch past the end
+    constexpr int n1 = N + 1, P1 = n1 * n1, MID = 2 * m + 2 * n1;
     // the lane's slots are recomputed here rather than kept live (in
     // registers) from the gather through the five passes
     int ts = tid;
     asm volatile("" : "+v"(ts));
-    int32_t oq[R], dq[R];
+    constexpr int RC = (PPB * NN + NT - 1) / NT, RO = (PPB * NX + NT - 1) / NT;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
-      oq[q] = (x < PPB * MMM && sE[lq] >= 0) ? xord[x - lq * MMM] : kSkip;
+    for (int q = 0; q < RC; ++q) {
+      const int x = ts + q * NT;
+      if (x >= PPB * NN) break;
+      const int lq = x / NN, t = x - lq * NN;
+      const int i = t % n1, j = (t / n1) % n1, k = t / P1;
+      const int64_t eq = sE[lq];
+      if (eq >= 0) zc[eq * NN + t] = X[lq * MMM + (i + 1) + m * (j + 1) + MM * (k + 1)];
+    }
+    int32_t dq[RO];
+#pragma unroll
+    for (int q = 0; q < RO; ++q) {
+      const int x = ts + q * NT, lq = min(x / NX, PPB - 1);
+      dq[q] = (x < PPB * NX && sE[lq] >= 0) ? xdest[sE[lq] * NX + (x - lq * NX)] : -1;
     }
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
-      dq[q] = oq[q] >= 0 ? xdest[sE[lq] * NX + oq[q]] : -1;
-    }
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int x = ts + q * NT, lq = min(x / MMM, PPB - 1);
-      if (oq[q] == kSkip) continue;
-      const T val = X[x];
-      if (oq[q] < 0)
-        zc[sE[lq] * NN + (-oq[q] - 1)] = val;
-      else if (dq[q] >= 0)
-        zx[dq[q]] = val;
+    for (int q = 0; q < RO; ++q) {
+      if (dq[q] < 0) continue;
+      const int x = ts + q * NT, lq = x / NX, o = x - lq * NX;
+      int slot;
+      if (o < MM) {
+        slot = o;
+      } else if (o < MM + n1 * MID) {
+        const int u = (o - MM) % MID, c = 1 + (o - MM) / MID;
+        const int ab = u < m ? u : (u < m + 2 * n1 ? m * (1 + (u - m) / 2) + ((u - m) & 1) * (m - 1)
+                                                 : m * (m - 1) + (u - m - 2 * n1));
+        slot = c * MM + ab;
+      } else {
+        slot = (m - 1) * MM + (o - MM - n1 * MID);
+      }
+      zx[dq[q]] = X[lq * MMM + slot];
     }
   }
 }
