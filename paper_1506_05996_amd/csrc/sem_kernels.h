@@ -1025,6 +1025,16 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
     for (int q = 0; q < RX; ++q)
       if (ij + q * P < NX) sX[le][ij + q * P] = xv[q];
   }
+  // with dpart: rd at the lane's interior nodes (1 <= k < N), loaded ahead of
+  // the sum so that the loop's loads do not wait one by one
+  const bool int_ij = (r1.w & kFlagInterior) != 0;
+  T rdk[n1];
+  if (dpart != nullptr && valid && int_ij) {
+    int ai, aj, ak;
+    unpack_coef(r1.y, ai, aj, ak);
+#pragma unroll
+    for (int k = 1; k < N; ++k) rdk[k] = rd[r1.x + ai * i + aj * j + ak * k];
+  }
   double zv[8];
   if (Zv != nullptr) {
 #pragma unroll
@@ -1089,7 +1099,7 @@ schwarz_sum_kernel(T* __restrict__ z, T* __restrict__ w, const T* __restrict__ z
     if (rr.w & kFlagInterior) {
       const T zv = (masked_interior && dir[rr.x + off]) ? T(0) : v;
       z[rr.x + off] = zv;
-      if (dpart != nullptr) dacc += (double)rd[rr.x + off] * (double)zv;
+      if (dpart != nullptr && k > 0 && k < N) dacc += (double)rdk[k] * (double)zv;
     } else {
       w[rr.z + off] = v;
     }
