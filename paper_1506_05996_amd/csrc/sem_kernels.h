@@ -735,20 +735,23 @@ gs_kernel(T* __restrict__ y, const T* __restrict__ w, const int32_t* __restrict_
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double d = 0.0;
   if (g < base_i) {
+    // every load of the node issued before any is used (node ids fit in 32 bits)
+    const uint8_t dg = dir[g];
+    const T pg = dpart != nullptr ? pd[g] : T(0);
     T s = 0;
-    if (g < V) {
+    if (g >= base_f) {  // face node (most shared nodes): both slots read, the second kept on interior faces
+      const uint32_t mm = (uint32_t)m * (uint32_t)m, q = (uint32_t)(g - base_f), f = q / mm, r = q - f * mm;
+      const T s0 = w[2 * (int64_t)f * mm + r], s1 = w[(2 * (int64_t)f + 1) * mm + r];
+      s = fcount[f] == 2 ? s0 + s1 : s0;
+    } else if (g < V) {
       for (int32_t q = vinc_off[g]; q < vinc_off[g + 1]; ++q) s += w[wvert_off + q];
-    } else if (g < base_f) {
-      const int64_t q = g - V, ed = q / m, r = q - ed * m;
-      for (int32_t x = einc_off[ed]; x < einc_off[ed + 1]; ++x) s += w[wedge_off + (int64_t)x * m + r];
     } else {
-      const int64_t mm = (int64_t)m * m, q = g - base_f, f = q / mm, r = q - f * mm;
-      s = w[2 * f * mm + r];
-      if (fcount[f] == 2) s += w[(2 * f + 1) * mm + r];
+      const uint32_t q = (uint32_t)(g - V), ed = q / (uint32_t)m, r = q - ed * (uint32_t)m;
+      for (int32_t x = einc_off[ed]; x < einc_off[ed + 1]; ++x) s += w[wedge_off + (int64_t)x * m + r];
     }
-    const T yv = dir[g] ? T(0) : op_value(oc, s, g, oc.scaled ? u[g] : T(0));
+    const T yv = dg ? T(0) : op_value(oc, s, g, oc.scaled ? u[g] : T(0));
     y[g] = yv;
-    if (dpart != nullptr) d = (double)pd[g] * (double)yv;
+    if (dpart != nullptr) d = (double)pg * (double)yv;
   }
   // with dpart: this workgroup's share of pd . y over the shared nodes
   if (dpart != nullptr) {
@@ -1138,21 +1141,20 @@ restrict_kernel(const T* __restrict__ r, double* __restrict__ Re, const int32_t*
     rv[k] = (rr.w & kFlagOwned) ? r[rr.x + ai * i + aj * j + ak * k] : T(0);
   }
   __syncthreads();
-  double acc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  // the lane's share of corner c: Phi_ci(t_i) Phi_cj(t_j) sum_k Phi_ck(t_k) r_k
+  double sk0 = 0.0, sk1 = 0.0;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
     const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
     if (rr.w & kFlagOwned) {
       const double v = (double)rv[k];
-#pragma unroll
-      for (int c = 0; c < 8; ++c)
-        acc[c] += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * v;
+      sk0 += sPhi[k] * v;
+      sk1 += sPhi[n1 + k] * v;
     }
   }
 #pragma unroll
-  for (int c = 0; c < 8; ++c) red[c][tid] = acc[c];
+  for (int c = 0; c < 8; ++c)
+    red[c][tid] = sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * ((c >> 2) ? sk1 : sk0);
   __syncthreads();
   if (tid < 8) {
     // four interleaved partial sums, combined in a fixed order
@@ -1194,7 +1196,7 @@ update_r_restrict_kernel(T* __restrict__ r, const T* __restrict__ w, const doubl
   const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
   const T al = (T)sc[2];
   T rv[n1], wv[n1];
-  int64_t gk[n1];
+  int32_t gk[n1];  // global node ids fit in 32 bits
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
     const int4 rr = k == 0 ? r0 : (k == N ? r2 : r1);
@@ -1206,9 +1208,8 @@ update_r_restrict_kernel(T* __restrict__ r, const T* __restrict__ w, const doubl
     wv[k] = own ? w[gk[k]] : T(0);
   }
   __syncthreads();
-  double acc[8], rsq = 0.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) acc[c] = 0.0;
+  // restriction as in restrict_kernel: two k-sums per lane, corner weights at the end
+  double sk0 = 0.0, sk1 = 0.0, rsq = 0.0;
 #pragma unroll
   for (int k = 0; k < n1; ++k) {
     if (gk[k] < 0) continue;
@@ -1216,12 +1217,12 @@ update_r_restrict_kernel(T* __restrict__ r, const T* __restrict__ w, const doubl
     r[gk[k]] = rn;
     const double v = (double)rn;
     rsq += v * v;
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-      acc[c] += sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * sPhi[(c >> 2) * n1 + k] * v;
+    sk0 += sPhi[k] * v;
+    sk1 += sPhi[n1 + k] * v;
   }
 #pragma unroll
-  for (int c = 0; c < 8; ++c) red[c][tid] = acc[c];
+  for (int c = 0; c < 8; ++c)
+    red[c][tid] = sPhi[(c & 1) * n1 + i] * sPhi[((c >> 1) & 1) * n1 + j] * ((c >> 2) ? sk1 : sk0);
   red[8][tid] = rsq;
   __syncthreads();
   if (tid < 9) {
