@@ -113,8 +113,9 @@ struct HostTables {
   std::vector<int32_t> face_nbr;         // [E][6][2] (element, local face) or -1
   std::vector<int32_t> ip;               // [E][(N+3)^3] global id or -1
   // the nx = (N+3)^3 - (N+1)^3 patch slots outside the element: their ordinal
-  // (xord[slot] >= 0, in lexicographic slot order; inside: -(local index) - 1;
-  // the device derives it in closed form) and, per patch, where each
+  // (xord[slot] >= 0, grouped by face plane, edge line and corner; inside:
+  // -(local index) - 1; the device derives the slot of an ordinal in closed
+  // form) and, per patch, where each
   // lands in the consumer layout [E][nx] of the element that holds it:
   // 6 face planes [(N+1)^2] at one layer in from that face (in-plane index
   // x_lo + (N+1) x_hi over the other two axes in increasing order), 12 edge

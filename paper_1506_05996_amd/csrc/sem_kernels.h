@@ -934,12 +934,13 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
   __syncthreads();
   // Results out, driven by the destination: the element's own nodes to zc in
   // element-local order (consecutive lanes, consecutive addresses), then the
-  // slots outside the element in their ordinal order (the whole first plane,
-  // 2m + 2(N+1) slots of each middle plane, the whole last plane), each to the
-  // consumer layout of the element that holds it (xdest read with consecutive
-  // addresses; NULL slots dropped).
+  // slots outside the element in their ordinal order, grouped by entity (6
+  // face planes of (N+1)^2, the lower of the other two axes fastest; 12 edge
+  // lines of N+1, edge 4 axis + side_lo + 2 side_hi; 8 corners), so that a
+  // wave's stores land in one neighbour's consumer block; xdest is read with
+  // consecutive addresses and NULL slots are dropped.
   {
-    constexpr int n1 = N + 1, P1 = n1 * n1, MID = 2 * m + 2 * n1;
+    constexpr int n1 = N + 1, P1 = n1 * n1;
     // the lane's slots are recomputed here rather than kept live (in
     // registers) from the gather through the five passes
     int ts = tid;
@@ -964,18 +965,26 @@ fdm_kernel(const T* __restrict__ r, T* __restrict__ zc, T* __restrict__ zx, cons
     for (int q = 0; q < RO; ++q) {
       if (dq[q] < 0) continue;
       const int x = ts + q * NT, lq = x / NX, o = x - lq * NX;
-      int slot;
-      if (o < MM) {
-        slot = o;
-      } else if (o < MM + n1 * MID) {
-        const int u = (o - MM) % MID, c = 1 + (o - MM) / MID;
-        const int ab = u < m ? u : (u < m + 2 * n1 ? m * (1 + (u - m) / 2) + ((u - m) & 1) * (m - 1)
-                                                 : m * (m - 1) + (u - m - 2 * n1));
-        slot = c * MM + ab;
+      int ca, cb, cc;  // slot coordinates (a, b, c)
+      if (o < 6 * P1) {
+        const int f = o / P1, t = o - f * P1, d = f >> 1, s = (f & 1) ? m - 1 : 0;
+        const int u = 1 + t % n1, v = 1 + t / n1;
+        ca = d == 0 ? s : u;
+        cb = d == 1 ? s : (d == 0 ? u : v);
+        cc = d == 2 ? s : v;
+      } else if (o < 6 * P1 + 12 * n1) {
+        const int y = o - 6 * P1, id = y / n1, ax = id >> 2, t = 1 + y % n1;
+        const int slo = (id & 1) ? m - 1 : 0, shi = (id & 2) ? m - 1 : 0;
+        ca = ax == 0 ? t : slo;
+        cb = ax == 1 ? t : (ax == 0 ? slo : shi);
+        cc = ax == 2 ? t : shi;
       } else {
-        slot = (m - 1) * MM + (o - MM - n1 * MID);
+        const int id = o - 6 * P1 - 12 * n1;
+        ca = (id & 1) ? m - 1 : 0;
+        cb = (id & 2) ? m - 1 : 0;
+        cc = (id & 4) ? m - 1 : 0;
       }
-      zx[dq[q]] = X[lq * MMM + slot];
+      zx[dq[q]] = X[lq * MMM + ca + m * cb + MM * cc];
     }
   }
 }

@@ -708,6 +708,36 @@ namespace {
 struct FaceMap {
   int perm[3], sign[3], off[3];
 };
+
+// Patch slot (a + m b + m^2 c, m = N + 3) of outside ordinal o, grouped by the
+// entity of the element the slot lies across: 6 face planes of (N+1)^2 (face
+// 2d + side, the lower of the other two axes fastest), 12 edge lines of N+1
+// (edge 4 axis + side_lo + 2 side_hi, position along the axis), 8 corners
+// (side_x + 2 side_y + 4 side_z).  The patch solve derives the same slot in
+// closed form when it writes the outside slots in ordinal order.
+int outside_patch_slot(int N, int o) {
+  const int m = N + 3, n1 = N + 1, P1 = n1 * n1;
+  int c[3];
+  if (o < 6 * P1) {
+    const int f = o / P1, t = o - f * P1, d = f >> 1;
+    const int lo = d == 0 ? 1 : 0, hi = d == 2 ? 1 : 2;
+    c[d] = (f & 1) ? m - 1 : 0;
+    c[lo] = 1 + t % n1;
+    c[hi] = 1 + t / n1;
+  } else if (o < 6 * P1 + 12 * n1) {
+    const int q = o - 6 * P1, id = q / n1, ax = id >> 2;
+    const int lo = ax == 0 ? 1 : 0, hi = ax == 2 ? 1 : 2;
+    c[ax] = 1 + q % n1;
+    c[lo] = (id & 1) ? m - 1 : 0;
+    c[hi] = (id & 2) ? m - 1 : 0;
+  } else {
+    const int id = o - 6 * P1 - 12 * n1;
+    c[0] = (id & 1) ? m - 1 : 0;
+    c[1] = (id & 2) ? m - 1 : 0;
+    c[2] = (id & 4) ? m - 1 : 0;
+  }
+  return c[0] + m * (c[1] + m * c[2]);
+}
 }  // namespace
 
 void build_patches(HostTables& T, const int64_t* hex) {
@@ -784,18 +814,11 @@ void build_patches(HostTables& T, const int64_t* hex) {
   const int64_t nx = pp - (int64_t)n1 * n1 * n1;
   T.nx = nx;
   T.xord.assign(pp, 0);
-  {
-    int32_t o = 0;
-    for (int c = 0; c < np; ++c)
-      for (int b = 0; b < np; ++b)
-        for (int a = 0; a < np; ++a) {
-          const int x = a + np * (b + np * c);
-          if (a >= 1 && a <= N + 1 && b >= 1 && b <= N + 1 && c >= 1 && c <= N + 1)
-            T.xord[x] = -((a - 1) + n1 * ((b - 1) + n1 * (c - 1))) - 1;
-          else
-            T.xord[x] = o++;
-        }
-  }
+  for (int c = 1; c <= N + 1; ++c)
+    for (int b = 1; b <= N + 1; ++b)
+      for (int a = 1; a <= N + 1; ++a)
+        T.xord[a + np * (b + np * c)] = -((a - 1) + n1 * ((b - 1) + n1 * (c - 1))) - 1;
+  for (int32_t o = 0; o < (int32_t)nx; ++o) T.xord[outside_patch_slot(N, o)] = o;
   // consumer slot of an outside patch slot: the element it lands in receives it
   // in its own frame, at one layer in from the face / edge / corner it shares
   // with the patch's element
