@@ -398,12 +398,19 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
   const int4* rp = reinterpret_cast<const int4*>(rec) + e * kClasses + cx + 3 * cy;
   const int4 r0 = rp[0], r1 = rp[9], r2 = rp[18];
   const T* Ge = G + (GEO ? e * 24 : e * 6 * NN + ij);
-  T P0[3], P1[3], Q0[3], Q1[3], C2[3], rij = 0;
+  // Rebuilt factors: along the lane's pencil (i, j) the Jacobian columns are
+  // dx/dxi = f0(t) P0 + f1(t) P1, dx/deta = f0(t) Q0 + f1(t) Q1 (f0,1 = (1 -+ t)/2)
+  // and dx/dzeta = C2 (no t), so the cofactor rows a0 = dx/deta x C2 and
+  // a1 = C2 x dx/dxi are linear in t and a2 = dx/dxi x dx/deta is quadratic:
+  // a0 = A0 + t A1, a1 = B0 + t B1, a2 = Z0 + t (Z1 + t Z2), and
+  // |J| = a2 . C2 = d0 + t (d1 + t d2).
+  T A0[3], A1[3], B0[3], B1[3], Z0[3], Z1[3], Z2[3], d0 = 0, d1 = 0, d2 = 0, rij = 0;
   if constexpr (GEO) {
     const T ti = tq[a], tj = tq[b];
     const T f0i = T(0.5) * (T(1) - ti), f1i = T(0.5) * (T(1) + ti);
     const T f0j = T(0.5) * (T(1) - tj), f1j = T(0.5) * (T(1) + tj);
     rij = tq[n1 + a] * tq[n1 + b];
+    T P0[3], P1[3], Q0[3], Q1[3], C2[3];
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       P0[q] = T(0.5) * ((Ge[1 * 3 + q] - Ge[0 * 3 + q]) * f0j + (Ge[3 * 3 + q] - Ge[2 * 3 + q]) * f1j);
@@ -413,6 +420,24 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
       C2[q] = T(0.5) * ((Ge[4 * 3 + q] - Ge[0 * 3 + q]) * f0i * f0j + (Ge[5 * 3 + q] - Ge[1 * 3 + q]) * f1i * f0j +
                         (Ge[6 * 3 + q] - Ge[2 * 3 + q]) * f0i * f1j + (Ge[7 * 3 + q] - Ge[3 * 3 + q]) * f1i * f1j);
     }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const int q1 = (q + 1) % 3, q2 = (q + 2) % 3;
+      const T x0 = Q0[q1] * C2[q2] - Q0[q2] * C2[q1], x1 = Q1[q1] * C2[q2] - Q1[q2] * C2[q1];
+      const T y0 = C2[q1] * P0[q2] - C2[q2] * P0[q1], y1 = C2[q1] * P1[q2] - C2[q2] * P1[q1];
+      const T z00 = P0[q1] * Q0[q2] - P0[q2] * Q0[q1], z11 = P1[q1] * Q1[q2] - P1[q2] * Q1[q1];
+      const T z01 = (P0[q1] * Q1[q2] - P0[q2] * Q1[q1]) + (P1[q1] * Q0[q2] - P1[q2] * Q0[q1]);
+      A0[q] = T(0.5) * (x0 + x1);
+      A1[q] = T(0.5) * (x1 - x0);
+      B0[q] = T(0.5) * (y0 + y1);
+      B1[q] = T(0.5) * (y1 - y0);
+      Z0[q] = T(0.25) * (z00 + z01 + z11);
+      Z1[q] = T(0.5) * (z11 - z00);
+      Z2[q] = T(0.25) * (z00 - z01 + z11);
+    }
+    d0 = Z0[0] * C2[0] + Z0[1] * C2[1] + Z0[2] * C2[2];
+    d1 = Z1[0] * C2[0] + Z1[1] * C2[1] + Z1[2] * C2[2];
+    d2 = Z2[0] * C2[0] + Z2[1] * C2[1] + Z2[2] * C2[2];
   }
   T uv[n1];
 #pragma unroll
@@ -476,17 +501,11 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
     T A, B, C;
     if constexpr (GEO) {
       const T tk = tq[k];
-      const T f0k = T(0.5) * (T(1) - tk), f1k = T(0.5) * (T(1) + tk);
-      T c0[3], c1[3];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        c0[q] = f0k * P0[q] + f1k * P1[q];
-        c1[q] = f0k * Q0[q] + f1k * Q1[q];
-      }
-      const T a0x = c1[1] * C2[2] - c1[2] * C2[1], a0y = c1[2] * C2[0] - c1[0] * C2[2], a0z = c1[0] * C2[1] - c1[1] * C2[0];
-      const T a1x = C2[1] * c0[2] - C2[2] * c0[1], a1y = C2[2] * c0[0] - C2[0] * c0[2], a1z = C2[0] * c0[1] - C2[1] * c0[0];
-      const T a2x = c0[1] * c1[2] - c0[2] * c1[1], a2y = c0[2] * c1[0] - c0[0] * c1[2], a2z = c0[0] * c1[1] - c0[1] * c1[0];
-      const T det = c0[0] * a0x + c0[1] * a0y + c0[2] * a0z;
+      const T a0x = A0[0] + tk * A1[0], a0y = A0[1] + tk * A1[1], a0z = A0[2] + tk * A1[2];
+      const T a1x = B0[0] + tk * B1[0], a1y = B0[1] + tk * B1[1], a1z = B0[2] + tk * B1[2];
+      const T a2x = Z0[0] + tk * (Z1[0] + tk * Z2[0]), a2y = Z0[1] + tk * (Z1[1] + tk * Z2[1]),
+              a2z = Z0[2] + tk * (Z1[2] + tk * Z2[2]);
+      const T det = d0 + tk * (d1 + tk * d2);
       T sc = rij * tq[n1 + k] * recip_pos(det);
       if constexpr (KN) sc *= pick(kv, k);  // kappa at the node (eq. (R))
       // G = sc M M^T (M: rows a0, a1, a2): (A, B, C) = sc M (M^T grad u)
@@ -538,9 +557,14 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
   if (valid) {
     const bool masked_interior = rec[(e * kClasses + kInteriorClass) * kRecInts + 3] & kFlagMaskedInterior;
     const ElemCoef<T> ec = elem_coef(oc, e);
+    // the pencil's records read again (cached) rather than kept live through the contractions
+    int64_t ro = e * kClasses + cx + 3 * cy;
+    asm volatile("" : "+v"(ro));
+    const int4* rq = reinterpret_cast<const int4*>(rec) + ro;
+    const int4 q0 = rq[0], q1 = rq[9], q2 = rq[18];
 #pragma unroll
     for (int k = 0; k < n1; ++k) {
-      const int4 r = k == 0 ? r0 : (k == N ? r2 : r1);
+      const int4 r = k == 0 ? q0 : (k == N ? q2 : q1);
       int ai, aj, ak;
       unpack_coef(r.y, ai, aj, ak);
       const int off = ai * a + aj * b + ak * k;
