@@ -857,6 +857,28 @@ void factor_coarse(sem_mesh m) {
   build_coarse_graph(m);
 }
 
+// D (n1 x n1, row-major) followed by the even/odd split that the line-phase
+// operator kernel uses for D and for D^T (see line_pairs in the kernels):
+// rows q < H = n1/2 of (D[q][m] + D[q][n1-1-m]) / 2 for m < H, D[q][H] when
+// n1 is odd, (D[q][m] - D[q][n1-1-m]) / 2 for m < H; for odd n1 a last row of
+// the middle output's (D[H][m] - D[H][n1-1-m]) / 2.  The other kernels read
+// only the first n1 x n1 entries.
+std::vector<double> d_with_split(const std::vector<double>& D, int n1) {
+  const int H = n1 / 2, od = n1 % 2;
+  std::vector<double> out(D);
+  for (int t = 0; t < 2; ++t) {
+    auto d = [&](int q, int m) { return t == 0 ? D[(size_t)q * n1 + m] : D[(size_t)m * n1 + q]; };
+    for (int q = 0; q < H; ++q) {
+      for (int m = 0; m < H; ++m) out.push_back(0.5 * (d(q, m) + d(q, n1 - 1 - m)));
+      if (od) out.push_back(d(q, H));
+      for (int m = 0; m < H; ++m) out.push_back(0.5 * (d(q, m) - d(q, n1 - 1 - m)));
+    }
+    if (od)
+      for (int m = 0; m < H; ++m) out.push_back(0.5 * (d(H, m) - d(H, n1 - 1 - m)));
+  }
+  return out;
+}
+
 void upload_all(sem_mesh m) {
   HostTables& T = m->T;
   SEM_HIP(hipSetDevice(m->device));
@@ -879,7 +901,8 @@ void upload_all(sem_mesh m) {
     m->vinc_ec.upload(ec.data(), ec.size());
   }
   m->G64.upload(T.G.data(), T.G.size());
-  m->D64.upload(T.D.data(), T.D.size());
+  const std::vector<double> Dx = d_with_split(T.D, T.n1);
+  m->D64.upload(Dx.data(), Dx.size());
   m->X864.upload(T.X8.data(), T.X8.size());
   std::vector<double> tq(T.t);
   tq.insert(tq.end(), T.rho.begin(), T.rho.end());
@@ -896,7 +919,7 @@ void upload_all(sem_mesh m) {
   if (m->fp32) {
     auto G32 = convert<float>(T.G);
     m->G32.upload(G32.data(), G32.size());
-    auto D32 = convert<float>(T.D);
+    auto D32 = convert<float>(Dx);
     m->D32.upload(D32.data(), D32.size());
     auto X832 = convert<float>(T.X8);
     m->X832.upload(X832.data(), X832.size());

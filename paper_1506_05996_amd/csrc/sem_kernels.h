@@ -361,6 +361,64 @@ ax_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, const T
 
 
 // ---------------------------------------------------------------------------
+// One 1D contraction of a line of n1 = N + 1 values by a matrix A with
+// A[N-q][N-m] = -A[q][m] (the GLL derivative matrix D and D^T: the points are
+// symmetric about 0).  With e_m = x_m + x_{N-m} and o_m = x_m - x_{N-m}
+// (m < H = n1/2), the outputs q and N-q are E + O and O - E, E = sum_m
+// Ap[q][m] e_m (+ A[q][H] x_H for odd n1), O = sum_m Am[q][m] o_m, so a line
+// costs H (n1 + 1) multiply-adds instead of n1^2.  tb: rows q < H of
+// [Ap[q][0..H-1], A[q][H] (odd n1), Am[q][0..H-1]], then for odd n1 the middle
+// output's Am[H][0..H-1] (read with wave-uniform addresses).  ld(m) reads
+// entry m of the line, st(q, v) writes output q; every read comes first, so
+// the output may overwrite the line.
+// Whether the line-phase operator kernel contracts its lines by output pairs:
+// everywhere but the FP64 kernels up to N = 9, which run at the 128-VGPR limit
+// of 4 waves per SIMD and measure faster with the row-by-row form (at 56^3,
+// N = 7: 0.628-0.636 ms against 0.635-0.651 ms; at N = 15 the pairs take
+// FP64 from 0.330 to 0.306 ms and FP32 from 0.171 to 0.151 ms).
+template <int N, typename T>
+constexpr bool line_pairs_on() {
+  return !(N <= 9 && sizeof(T) == 8);
+}
+
+template <int n1>
+constexpr int dsplit_size() {
+  return (n1 / 2) * (2 * (n1 / 2) + n1 % 2) + (n1 % 2) * (n1 / 2);
+}
+
+template <int n1, typename T, typename Ld, typename St>
+__device__ __forceinline__ void line_pairs(const T* __restrict__ tb, Ld ld, St st) {
+  constexpr int H = n1 / 2, OD = n1 % 2, RW = 2 * H + OD;
+  T e[H], o[H], xm = T(0);
+#pragma unroll
+  for (int m = 0; m < H; ++m) {
+    const T l = ld(m), r = ld(n1 - 1 - m);
+    e[m] = l + r;
+    o[m] = l - r;
+  }
+  if constexpr (OD) xm = ld(H);
+#pragma unroll 1
+  for (int q = 0; q < H; ++q) {
+    const T* row = tb + q * RW;
+    T E = 0, O = 0;
+#pragma unroll
+    for (int m = 0; m < H; ++m) E += row[m] * e[m];
+    if constexpr (OD) E += row[H] * xm;
+#pragma unroll
+    for (int m = 0; m < H; ++m) O += row[H + OD + m] * o[m];
+    st(q, E + O);
+    st(n1 - 1 - q, O - E);
+  }
+  if constexpr (OD) {
+    const T* row = tb + H * RW;
+    T O = 0;
+#pragma unroll
+    for (int m = 0; m < H; ++m) O += row[m] * o[m];
+    st(H, O);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Operator kernel by line phases, eq. (R) / Algorithm 2.  Each 1D contraction
 // is done by lanes that own whole lines of the element, so the derivative
 // matrix is wave-uniform (scalar registers) and every line is read from LDS
@@ -385,6 +443,7 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
                OpCoef<T> oc) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   constexpr int LS = n1 + 1, PS = n1 * LS, BS = n1 * PS;
+  constexpr bool PAIRS = line_pairs_on<N, T>();
   __shared__ T sX[EPB][BS];
   __shared__ T sZ[EPB][BS];
   __shared__ double sRed[EPB * P];
@@ -457,36 +516,53 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
 #pragma unroll
   for (int k = 0; k < n1; ++k) X[k * PS + b * LS + a] = uv[k];
   __syncthreads();
-  // Forward contractions loop over the output index q with row q of D in
-  // scalar registers (one row live at a time); the line sits in registers.
-  {  // eta lines: lane (i = a, k = b)
-    T v[n1];
+  // Line contractions: by output pairs (line_pairs, with the even/odd split of
+  // D and of D^T stored after D), or row by row with the full D (the form
+  // that keeps more independent accumulators; see line_pairs_on); the line
+  // sits in registers.
+  const T* Dsp = Dg + n1 * n1;             // D
+  const T* DTsp = Dsp + dsplit_size<n1>();  // D^T
+  if constexpr (PAIRS) {
+    // eta lines: lane (i = a, k = b)
+    line_pairs<n1, T>(Dsp, [&](int m) { return X[b * PS + m * LS + a]; },
+                      [&](int q, T v) { Z[b * PS + q * LS + a] = v; });
+    __syncthreads();
+    // xi lines: lane (j = a, k = b), in place
+    line_pairs<n1, T>(Dsp, [&](int m) { return X[b * PS + a * LS + m]; },
+                      [&](int q, T v) { X[b * PS + a * LS + q] = v; });
+    __syncthreads();
+  } else {
+    // Forward contractions loop over the output index q with row q of D in
+    // scalar registers (one row live at a time).
+    {  // eta lines: lane (i = a, k = b)
+      T v[n1];
 #pragma unroll
-    for (int m = 0; m < n1; ++m) v[m] = X[b * PS + m * LS + a];
+      for (int m = 0; m < n1; ++m) v[m] = X[b * PS + m * LS + a];
 #pragma unroll 1
-    for (int q = 0; q < n1; ++q) {
-      const T* Dq = Dg + q * n1;
-      T s = 0;
+      for (int q = 0; q < n1; ++q) {
+        const T* Dq = Dg + q * n1;
+        T s = 0;
 #pragma unroll
-      for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
-      Z[b * PS + q * LS + a] = s;
+        for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
+        Z[b * PS + q * LS + a] = s;
+      }
     }
-  }
-  __syncthreads();
-  {  // xi lines: lane (j = a, k = b), in place
-    T v[n1];
+    __syncthreads();
+    {  // xi lines: lane (j = a, k = b), in place
+      T v[n1];
 #pragma unroll
-    for (int m = 0; m < n1; ++m) v[m] = X[b * PS + a * LS + m];
+      for (int m = 0; m < n1; ++m) v[m] = X[b * PS + a * LS + m];
 #pragma unroll 1
-    for (int q = 0; q < n1; ++q) {
-      const T* Dq = Dg + q * n1;
-      T s = 0;
+      for (int q = 0; q < n1; ++q) {
+        const T* Dq = Dg + q * n1;
+        T s = 0;
 #pragma unroll
-      for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
-      X[b * PS + a * LS + q] = s;
+        for (int m = 0; m < n1; ++m) s += Dq[m] * v[m];
+        X[b * PS + a * LS + q] = s;
+      }
     }
+    __syncthreads();
   }
-  __syncthreads();
   T rw[n1];
 #pragma unroll
   for (int k = 0; k < n1; ++k) rw[k] = T(0);
@@ -527,10 +603,15 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
     for (int m = 0; m < n1; ++m) rw[m] += Dk[m] * C;
   }
   __syncthreads();
-  // Transposed contractions loop over the input index m: row m of D in scalar
-  // registers scales line entry m into all outputs; each lane owns its line,
-  // so the results overwrite it after the loop.
-  {  // transposed xi lines (lane (j = a, k = b)) and eta lines (lane (i = a, k = b)), in place
+  // transposed xi lines (lane (j = a, k = b)) and eta lines (lane (i = a, k = b)), in place
+  if constexpr (PAIRS) {
+    line_pairs<n1, T>(DTsp, [&](int m) { return X[b * PS + a * LS + m]; },
+                      [&](int q, T v) { X[b * PS + a * LS + q] = v; });
+    line_pairs<n1, T>(DTsp, [&](int m) { return Z[b * PS + m * LS + a]; },
+                      [&](int q, T v) { Z[b * PS + q * LS + a] = v; });
+  } else {
+    // loop over the input index m: row m of D in scalar registers scales line
+    // entry m into all outputs; the results overwrite the line after the loop
     T sx[n1], sz[n1];
 #pragma unroll
     for (int q = 0; q < n1; ++q) sx[q] = sz[q] = T(0);
