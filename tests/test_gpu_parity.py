@@ -286,11 +286,13 @@ def test_autotuned_tile_gives_identical_results():
 
 
 @pytest.mark.parametrize("tile", ["TILE_GEO", "TILE_LINE_GEO", "TILE_LINE"])
-@pytest.mark.parametrize("N", [2, 4, 7, 9, 15])
+@pytest.mark.parametrize("N", [2, 4, 7, 9, 10, 15])
 def test_operator_kernel_variants(N, tile):
     """The operator kernels that rebuild G from the vertices (plane-staged and
     line-phase) and the line-phase kernel with stored factors match the oracle
-    (FP64 to 1e-12, FP32 to the FP32 bound) on a rotated, permuted mesh."""
+    (FP64 to 1e-12, FP32 to the FP32 bound) on a rotated, permuted mesh.  N = 10
+    takes the FP64 line contractions by output pairs with an odd line length
+    (the middle output and column); N = 2 and 4 take it in FP32."""
     from paper_1506_05996_amd import sem
     dev = _dev()
     m = meshgen.cube_mesh((2, 3, 2), perturb=0.15, seed=81)
