@@ -381,6 +381,15 @@ constexpr bool line_pairs_on() {
   return !(N <= 9 && sizeof(T) == 8);
 }
 
+// Whether the pencil's nodes k and N-k are processed together (the zeta
+// derivative and the zeta part of D^T C by output pairs as well): from N = 10,
+// where the kernel has registers to spare (N = 15: 0.303-0.308 -> 0.288-0.289 ms
+// FP64, 0.150-0.154 -> 0.139 ms FP32); at N = 7 FP32 it measured 2-3% slower.
+template <int N, typename T>
+constexpr bool zeta_pairs_on() {
+  return line_pairs_on<N, T>() && N >= 10;
+}
+
 template <int n1>
 constexpr int dsplit_size() {
   return (n1 / 2) * (2 * (n1 / 2) + n1 % 2) + (n1 % 2) * (n1 / 2);
@@ -443,7 +452,7 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
                OpCoef<T> oc) {
   constexpr int n1 = N + 1, P = n1 * n1, NN = P * n1;
   constexpr int LS = n1 + 1, PS = n1 * LS, BS = n1 * PS;
-  constexpr bool PAIRS = line_pairs_on<N, T>();
+  constexpr bool PAIRS = line_pairs_on<N, T>(), ZPAIRS = zeta_pairs_on<N, T>();
   __shared__ T sX[EPB][BS];
   __shared__ T sZ[EPB][BS];
   __shared__ double sRed[EPB * P];
@@ -566,41 +575,120 @@ ax_line_kernel(const T* __restrict__ u, T* __restrict__ y, T* __restrict__ w, co
   T rw[n1];
 #pragma unroll
   for (int k = 0; k < n1; ++k) rw[k] = T(0);
-#pragma unroll 1
-  for (int k = 0; k < n1; ++k) {
-    const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
-    const int o = k * PS + b * LS + a;
-    const T ur = X[o], us = Z[o];
-    T ut = 0;
+  if constexpr (ZPAIRS) {
+    // nodes k and N-k of the pencil together: their zeta derivatives are one
+    // output pair of line_pairs on u, and the zeta part of D^T C takes
+    // C_k - C_{N-k} against the even part of row k of D and C_k + C_{N-k}
+    // against the odd part (rw_m = SE_m + SO_m, rw_{N-m} = SE_m - SO_m)
+    constexpr int H = n1 / 2, OD = n1 % 2, RW = 2 * H + OD;
+    T ue[H], uo[H], SE[H], SO[H], SM = T(0);
 #pragma unroll
-    for (int m = 0; m < n1; ++m) ut += Dk[m] * uv[m];
-    T A, B, C;
-    if constexpr (GEO) {
-      const T tk = tq[k];
-      const T a0x = A0[0] + tk * A1[0], a0y = A0[1] + tk * A1[1], a0z = A0[2] + tk * A1[2];
-      const T a1x = B0[0] + tk * B1[0], a1y = B0[1] + tk * B1[1], a1z = B0[2] + tk * B1[2];
-      const T a2x = Z0[0] + tk * (Z1[0] + tk * Z2[0]), a2y = Z0[1] + tk * (Z1[1] + tk * Z2[1]),
-              a2z = Z0[2] + tk * (Z1[2] + tk * Z2[2]);
-      const T det = d0 + tk * (d1 + tk * d2);
-      T sc = rij * tq[n1 + k] * recip_pos(det);
-      if constexpr (KN) sc *= pick(kv, k);  // kappa at the node (eq. (R))
-      // G = sc M M^T (M: rows a0, a1, a2): (A, B, C) = sc M (M^T grad u)
-      const T vx = ur * a0x + us * a1x + ut * a2x, vy = ur * a0y + us * a1y + ut * a2y,
-              vz = ur * a0z + us * a1z + ut * a2z;
-      A = sc * (a0x * vx + a0y * vy + a0z * vz);
-      B = sc * (a1x * vx + a1y * vy + a1z * vz);
-      C = sc * (a2x * vx + a2y * vy + a2z * vz);
-    } else {
-      const T* Gk = Ge + k * P;
-      const T g0 = Gk[0 * NN], g1 = Gk[1 * NN], g2 = Gk[2 * NN], g3 = Gk[3 * NN], g4 = Gk[4 * NN], g5 = Gk[5 * NN];
-      A = g0 * ur + g1 * us + g2 * ut;
-      B = g1 * ur + g3 * us + g4 * ut;
-      C = g2 * ur + g4 * us + g5 * ut;
+    for (int m = 0; m < H; ++m) {
+      ue[m] = uv[m] + uv[N - m];
+      uo[m] = uv[m] - uv[N - m];
+      SE[m] = SO[m] = T(0);
     }
-    X[o] = A;
-    Z[o] = B;
+    // A and B of node k to X and Z in place; returns C
+    auto node = [&](int k, T ut) -> T {
+      const int o = k * PS + b * LS + a;
+      const T ur = X[o], us = Z[o];
+      T A, B, C;
+      if constexpr (GEO) {
+        const T tk = tq[k];
+        const T a0x = A0[0] + tk * A1[0], a0y = A0[1] + tk * A1[1], a0z = A0[2] + tk * A1[2];
+        const T a1x = B0[0] + tk * B1[0], a1y = B0[1] + tk * B1[1], a1z = B0[2] + tk * B1[2];
+        const T a2x = Z0[0] + tk * (Z1[0] + tk * Z2[0]), a2y = Z0[1] + tk * (Z1[1] + tk * Z2[1]),
+                a2z = Z0[2] + tk * (Z1[2] + tk * Z2[2]);
+        const T det = d0 + tk * (d1 + tk * d2);
+        T sc = rij * tq[n1 + k] * recip_pos(det);
+        if constexpr (KN) sc *= pick(kv, k);  // kappa at the node (eq. (R))
+        // G = sc M M^T (M: rows a0, a1, a2): (A, B, C) = sc M (M^T grad u)
+        const T vx = ur * a0x + us * a1x + ut * a2x, vy = ur * a0y + us * a1y + ut * a2y,
+                vz = ur * a0z + us * a1z + ut * a2z;
+        A = sc * (a0x * vx + a0y * vy + a0z * vz);
+        B = sc * (a1x * vx + a1y * vy + a1z * vz);
+        C = sc * (a2x * vx + a2y * vy + a2z * vz);
+      } else {
+        const T* Gk = Ge + k * P;
+        const T g0 = Gk[0 * NN], g1 = Gk[1 * NN], g2 = Gk[2 * NN], g3 = Gk[3 * NN], g4 = Gk[4 * NN], g5 = Gk[5 * NN];
+        A = g0 * ur + g1 * us + g2 * ut;
+        B = g1 * ur + g3 * us + g4 * ut;
+        C = g2 * ur + g4 * us + g5 * ut;
+      }
+      X[o] = A;
+      Z[o] = B;
+      return C;
+    };
+#pragma unroll 1
+    for (int k = 0; k < H; ++k) {
+      const T* row = Dsp + k * RW;  // wave-uniform: scalar loads
+      T E = 0, O = 0;
 #pragma unroll
-    for (int m = 0; m < n1; ++m) rw[m] += Dk[m] * C;
+      for (int m = 0; m < H; ++m) E += row[m] * ue[m];
+      if constexpr (OD) E += row[H] * uv[H];
+#pragma unroll
+      for (int m = 0; m < H; ++m) O += row[H + OD + m] * uo[m];
+      const T C1 = node(k, E + O), C2 = node(N - k, O - E);
+      const T cd = C1 - C2, cs = C1 + C2;
+#pragma unroll
+      for (int m = 0; m < H; ++m) {
+        SE[m] += row[m] * cd;
+        SO[m] += row[H + OD + m] * cs;
+      }
+      if constexpr (OD) SM += row[H] * cd;
+    }
+    if constexpr (OD) {  // the middle node (its row of D is odd)
+      const T* row = Dsp + H * RW;
+      T O = 0;
+#pragma unroll
+      for (int m = 0; m < H; ++m) O += row[m] * uo[m];
+      const T C = node(H, O);
+#pragma unroll
+      for (int m = 0; m < H; ++m) SO[m] += row[m] * C;
+      rw[H] = SM;
+    }
+#pragma unroll
+    for (int m = 0; m < H; ++m) {
+      rw[m] = SE[m] + SO[m];
+      rw[N - m] = SE[m] - SO[m];
+    }
+  } else {
+#pragma unroll 1
+    for (int k = 0; k < n1; ++k) {
+      const T* Dk = Dg + k * n1;  // wave-uniform: scalar loads
+      const int o = k * PS + b * LS + a;
+      const T ur = X[o], us = Z[o];
+      T ut = 0;
+#pragma unroll
+      for (int m = 0; m < n1; ++m) ut += Dk[m] * uv[m];
+      T A, B, C;
+      if constexpr (GEO) {
+        const T tk = tq[k];
+        const T a0x = A0[0] + tk * A1[0], a0y = A0[1] + tk * A1[1], a0z = A0[2] + tk * A1[2];
+        const T a1x = B0[0] + tk * B1[0], a1y = B0[1] + tk * B1[1], a1z = B0[2] + tk * B1[2];
+        const T a2x = Z0[0] + tk * (Z1[0] + tk * Z2[0]), a2y = Z0[1] + tk * (Z1[1] + tk * Z2[1]),
+                a2z = Z0[2] + tk * (Z1[2] + tk * Z2[2]);
+        const T det = d0 + tk * (d1 + tk * d2);
+        T sc = rij * tq[n1 + k] * recip_pos(det);
+        if constexpr (KN) sc *= pick(kv, k);  // kappa at the node (eq. (R))
+        // G = sc M M^T (M: rows a0, a1, a2): (A, B, C) = sc M (M^T grad u)
+        const T vx = ur * a0x + us * a1x + ut * a2x, vy = ur * a0y + us * a1y + ut * a2y,
+                vz = ur * a0z + us * a1z + ut * a2z;
+        A = sc * (a0x * vx + a0y * vy + a0z * vz);
+        B = sc * (a1x * vx + a1y * vy + a1z * vz);
+        C = sc * (a2x * vx + a2y * vy + a2z * vz);
+      } else {
+        const T* Gk = Ge + k * P;
+        const T g0 = Gk[0 * NN], g1 = Gk[1 * NN], g2 = Gk[2 * NN], g3 = Gk[3 * NN], g4 = Gk[4 * NN], g5 = Gk[5 * NN];
+        A = g0 * ur + g1 * us + g2 * ut;
+        B = g1 * ur + g3 * us + g4 * ut;
+        C = g2 * ur + g4 * us + g5 * ut;
+      }
+      X[o] = A;
+      Z[o] = B;
+#pragma unroll
+      for (int m = 0; m < n1; ++m) rw[m] += Dk[m] * C;
+    }
   }
   __syncthreads();
   // transposed xi lines (lane (j = a, k = b)) and eta lines (lane (i = a, k = b)), in place
